@@ -1,0 +1,73 @@
+"""Method of lines with the sparse RBF-FD Laplacian (Sec. 4.2, eq. kernel_mol).
+
+L_X is the N x N matrix whose row k holds the weights of stencil k at the
+stencil's node indices (Sec. 4, the paragraph after the first-row weights).
+The semi-discrete system du_s/dt = D_s L_X u_s + R_s(u) is advanced with the
+classical fourth-order Runge-Kutta method (the paper uses BDF4 and SBDF2; the
+explicit RK4 is the reading for these workloads).
+
+Reactions:
+  none         R = 0 (heat equation)
+  schnakenberg R_u = gamma (a - u + u^2 v),  R_v = gamma (b - u^2 v)
+  turing       the activator-inhibitor system of Sec. 7 (eqs. turing1,
+               turing2): R_u = alpha u (1 - tau1 v^2) + v (1 - tau2 u),
+               R_v = beta v (1 + alpha tau1 u v / beta) + u (gamma + tau2 v)
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+__all__ = ["assemble", "reaction", "rhs", "rk4", "laplacian_apply"]
+
+
+def assemble(idx: np.ndarray, w: np.ndarray, N: int | None = None) -> sp.csr_matrix:
+    """Sparse L_X with row i = weights of stencil i at its node indices."""
+    Nr, n = idx.shape
+    N = Nr if N is None else N
+    rows = np.repeat(np.arange(Nr), n)
+    return sp.csr_matrix((w.ravel(), (rows, idx.ravel())), shape=(Nr, N))
+
+
+def laplacian_apply(idx, w, u):
+    """(L_X u)_i = sum_j w_ij u_{idx_ij}, summed in slot order."""
+    acc = np.zeros(len(idx))
+    for k in range(idx.shape[1]):
+        acc = acc + w[:, k] * u[idx[:, k]]
+    return acc
+
+
+def reaction(kind: str, Y, params):
+    if kind == "none":
+        return [np.zeros_like(y) for y in Y]
+    if kind == "schnakenberg":
+        a, b, g = params["a"], params["b"], params["gamma"]
+        u, v = Y
+        u2v = u * u * v
+        return [g * (a - u + u2v), g * (b - u2v)]
+    if kind == "turing":
+        al, be, ga = params["alpha"], params["beta"], params["gamma"]
+        t1, t2 = params["tau1"], params["tau2"]
+        u, v = Y
+        return [al * u * (1.0 - t1 * v * v) + v * (1.0 - t2 * u),
+                be * v * (1.0 + al * t1 / be * u * v) + u * (ga + t2 * v)]
+    raise ValueError(kind)
+
+
+def rhs(L, Y, D, kind, params):
+    R = reaction(kind, Y, params)
+    return [D[s] * (L @ Y[s]) + R[s] for s in range(len(Y))]
+
+
+def rk4(L, Y0, D, kind="none", params=None, dt=1e-4, nsteps=1):
+    """Classical RK4: k1 = f(y), k2 = f(y + dt/2 k1), k3 = f(y + dt/2 k2),
+    k4 = f(y + dt k3), y+ = y + dt/6 (k1 + 2 k2 + 2 k3 + k4)."""
+    Y = [np.array(y, dtype=np.float64) for y in Y0]
+    S = len(Y)
+    for _ in range(nsteps):
+        k1 = rhs(L, Y, D, kind, params)
+        k2 = rhs(L, [Y[s] + 0.5 * dt * k1[s] for s in range(S)], D, kind, params)
+        k3 = rhs(L, [Y[s] + 0.5 * dt * k2[s] for s in range(S)], D, kind, params)
+        k4 = rhs(L, [Y[s] + dt * k3[s] for s in range(S)], D, kind, params)
+        Y = [Y[s] + (dt / 6.0) * (k1[s] + 2.0 * k2[s] + 2.0 * k3[s] + k4[s]) for s in range(S)]
+    return Y

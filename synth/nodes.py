@@ -1,0 +1,211 @@
+"""Seeded node sets with unit normals on closed surfaces.
+
+The paper's own node sets (maximal-determinant nodes, the red blood cell,
+the double torus, the bumpy sphere, Frog and Bunny point clouds) are not
+available, so these generators stand in for them with the same kinds of
+structure: quasi-uniform nodes on the sphere (Fibonacci spiral), a jittered
+parametric grid on the torus of Sec. 6 (eq. torus), ellipsoids, and a
+Poisson-disk-thinned point cloud on an implicit surface (standing in for the
+reconstructed point clouds of Sec. 7.2).
+
+Every function returns ``(X, nrm)`` as float64 arrays of shape ``(N, 3)``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "fibonacci_sphere",
+    "jittered_torus",
+    "torus_grid_for_count",
+    "ellipsoid",
+    "blob",
+    "planar_patch",
+    "surface_batch",
+]
+
+
+def fibonacci_sphere(N: int, radius: float = 1.0):
+    """Fibonacci-spiral nodes on a sphere: z_i = 1-(2i+1)/N, lon_i = i*pi*(3-sqrt 5).
+
+    Normals are the exact outward unit normals (the node direction).
+    """
+    i = np.arange(N, dtype=np.float64)
+    z = 1.0 - (2.0 * i + 1.0) / N
+    lon = i * (math.pi * (3.0 - math.sqrt(5.0)))
+    s = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    U = np.stack([s * np.cos(lon), s * np.sin(lon), z], axis=1)
+    return radius * U, U.copy()
+
+
+def jittered_torus(n_phi: int, n_lam: int, R: float = 1.0, r: float = 1.0 / 3.0,
+                   jitter: float = 0.25, seed: int = 3):
+    """Parametric torus (R + r cos phi) cos lam, (R + r cos phi) sin lam, r sin phi.
+
+    A tensor grid of n_phi x n_lam cells over [-pi, pi)^2 in (phi, lam), each
+    node moved by U(-jitter, jitter) cells in both directions (seeded).
+    Normals are analytic: (cos phi cos lam, cos phi sin lam, sin phi).
+    """
+    rng = np.random.default_rng(seed)
+    dphi = 2.0 * math.pi / n_phi
+    dlam = 2.0 * math.pi / n_lam
+    P, L = np.meshgrid(np.arange(n_phi, dtype=np.float64), np.arange(n_lam, dtype=np.float64),
+                       indexing="ij")
+    P = P.ravel()
+    L = L.ravel()
+    jp = rng.uniform(-jitter, jitter, size=P.shape)
+    jl = rng.uniform(-jitter, jitter, size=L.shape)
+    phi = -math.pi + (P + 0.5 + jp) * dphi
+    lam = -math.pi + (L + 0.5 + jl) * dlam
+    c = R + r * np.cos(phi)
+    X = np.stack([c * np.cos(lam), c * np.sin(lam), r * np.sin(phi)], axis=1)
+    nrm = np.stack([np.cos(phi) * np.cos(lam), np.cos(phi) * np.sin(lam), np.sin(phi)], axis=1)
+    return X, nrm
+
+
+def torus_grid_for_count(N: int, R: float, r: float):
+    """(n_phi, n_lam) with n_phi * n_lam close to N and cells roughly square."""
+    aspect = R / r  # mean toroidal / poloidal circumference
+    n_phi = max(3, int(round(math.sqrt(N / aspect))))
+    n_lam = max(3, int(round(N / n_phi)))
+    return n_phi, n_lam
+
+
+def ellipsoid(N: int, a: float, b: float, c: float):
+    """Fibonacci nodes mapped to the ellipsoid x^2/a^2 + y^2/b^2 + z^2/c^2 = 1.
+
+    Normals are the normalised gradient (x/a^2, y/b^2, z/c^2).
+    """
+    U, _ = fibonacci_sphere(N)
+    X = U * np.array([a, b, c])
+    g = X / np.array([a * a, b * b, c * c])
+    return X, g / np.linalg.norm(g, axis=1, keepdims=True)
+
+
+def _blob_f_grad(P, C, s2):
+    d = P[:, None, :] - C[None, :, :]
+    e = np.exp(-np.sum(d * d, axis=2) / s2)
+    f = e.sum(axis=1)
+    g = -2.0 / s2 * np.einsum("ij,ijk->ik", e, d)
+    return f, g
+
+
+def blob(N: int, seed: int = 4, ncentres: int = 8, s2: float = 0.3, level: float = 0.5,
+         oversample: float = 3.0):
+    """Point cloud on the implicit surface sum_i exp(-|x-c_i|^2/s2) = level.
+
+    Centres are U([-1,1]^3) (seeded).  Candidates drawn uniformly in a box
+    around the centres are kept near the level set, Newton-projected onto it
+    until |f - level| < 1e-13, and thinned on a uniform grid (at most one node
+    per cell, in a seeded random order) to exactly N nodes.  Normals are
+    -grad f / |grad f| (outward, since f decreases outwards).
+    """
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(-1.0, 1.0, size=(ncentres, 3))
+    lo = C.min(axis=0) - 1.2
+    hi = C.max(axis=0) + 1.2
+    pts = []
+    have = 0
+    need = int(oversample * N) + 1000
+    chunk = 1 << 20
+    while have < need:
+        P = rng.uniform(lo, hi, size=(chunk, 3))
+        f, _ = _blob_f_grad(P, C, s2)
+        P = P[np.abs(f - level) < 0.25]
+        for _ in range(60):
+            f, g = _blob_f_grad(P, C, s2)
+            gg = np.sum(g * g, axis=1)
+            ok = gg > 1e-8
+            P = P[ok]
+            f, g, gg = f[ok], g[ok], gg[ok]
+            step = ((f - level) / gg)[:, None] * g
+            step_n = np.linalg.norm(step, axis=1)
+            # damp long steps so that candidates do not jump between sheets
+            scale = np.minimum(1.0, 0.1 / np.maximum(step_n, 1e-300))[:, None]
+            P = P - scale * step
+            if np.all(np.abs(f - level) < 1e-13) and np.all(step_n < 1e-12):
+                break
+        f, g = _blob_f_grad(P, C, s2)
+        P = P[np.abs(f - level) < 1e-13]
+        pts.append(P)
+        have += len(P)
+    P = np.concatenate(pts)[:need]
+    # area-scale estimate from the candidate count is not needed: thin with a
+    # cell size found by bisection so that at least N cells are occupied.
+    perm = rng.permutation(len(P))
+    P = P[perm]
+    ext = hi - lo
+
+    def occupied(h):
+        key = np.floor((P - lo) / h).astype(np.int64)
+        dims = np.floor(ext / h).astype(np.int64) + 2
+        lin = (key[:, 0] * dims[1] + key[:, 1]) * dims[2] + key[:, 2]
+        _, first = np.unique(lin, return_index=True)
+        return np.sort(first)
+
+    h_lo, h_hi = 1e-6, float(ext.max())
+    keep = None
+    for _ in range(60):
+        h = math.sqrt(h_lo * h_hi)
+        k = occupied(h)
+        if len(k) >= N:
+            h_lo, keep = h, k
+        else:
+            h_hi = h
+        if h_hi / h_lo < 1.0 + 1e-4:
+            break
+    if keep is None:
+        raise RuntimeError("blob: not enough candidates")
+    keep = keep[np.sort(rng.permutation(len(keep))[:N])]
+    X = P[keep]
+    _, g = _blob_f_grad(X, C, s2)
+    nrm = -g / np.linalg.norm(g, axis=1, keepdims=True)
+    return np.ascontiguousarray(X), np.ascontiguousarray(nrm)
+
+
+def planar_patch(n_side: int, spacing: float = 0.125, seed: int | None = None, jitter: float = 0.0):
+    """A planar patch in z = 0 (normals +z): a lattice, optionally jittered."""
+    g = (np.arange(n_side, dtype=np.float64) - (n_side - 1) / 2.0) * spacing
+    Xg, Yg = np.meshgrid(g, g, indexing="ij")
+    X = np.stack([Xg.ravel(), Yg.ravel(), np.zeros(n_side * n_side)], axis=1)
+    if seed is not None and jitter > 0:
+        rng = np.random.default_rng(seed)
+        X[:, :2] += rng.uniform(-jitter, jitter, size=(len(X), 2)) * spacing
+    nrm = np.zeros_like(X)
+    nrm[:, 2] = 1.0
+    return X, nrm
+
+
+def surface_batch(count: int = 64, seed: int = 5, n_min: int = 2000, n_max: int = 60000,
+                  stencil_sizes=(31, 50, 70, 101)):
+    """A seeded batch of spheres, tori and ellipsoids of uneven size.
+
+    Sphere radius, ellipsoid semi-axes and torus major radius are U[0.5, 2];
+    the torus minor radius is R*U[0.2, 0.45].  N is floor(exp(U[ln n_min,
+    ln n_max])) and the stencil size is drawn uniformly from stencil_sizes.
+    Returns a list of dicts with keys kind, X, nrm, n, params.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        kind = ("sphere", "torus", "ellipsoid")[int(rng.integers(0, 3))]
+        N = int(math.floor(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        n = int(stencil_sizes[int(rng.integers(0, len(stencil_sizes)))])
+        if kind == "sphere":
+            rad = float(rng.uniform(0.5, 2.0))
+            X, nrm = fibonacci_sphere(N, rad)
+            params = {"radius": rad}
+        elif kind == "torus":
+            R = float(rng.uniform(0.5, 2.0))
+            r = R * float(rng.uniform(0.2, 0.45))
+            n_phi, n_lam = torus_grid_for_count(N, R, r)
+            X, nrm = jittered_torus(n_phi, n_lam, R, r, seed=int(rng.integers(0, 2**31)))
+            params = {"R": R, "r": r}
+        else:
+            ax = rng.uniform(0.5, 2.0, size=3)
+            X, nrm = ellipsoid(N, *ax)
+            params = {"axes": ax.tolist()}
+        out.append({"kind": kind, "X": X, "nrm": nrm, "n": n, "params": params})
+    return out

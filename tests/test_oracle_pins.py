@@ -1,0 +1,333 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each check is chosen so that a plausible mistake in the oracle (a dropped
+projection, a wrong sign, a transposed operand, a lost border column) fails
+at least one of them.  None of them re-types the oracle's own formulas.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle.knn import knn, knn_bruteforce
+from oracle.shape import bisect_eps, kappa2, stencil_kappa
+from oracle.stepper import assemble, reaction, rk4
+from oracle.truth import stencil_weights_mp
+from oracle.weights import (build_weights, phi, poly_border, psi, stencil_weights,
+                            stencil_weights_row1)
+from synth import (fibonacci_sphere, jittered_torus, planar_patch, real_sph_harm,
+                   schnakenberg_ic)
+
+U64 = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_facts.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLDEN):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split()
+            out[k] = float(v)
+    return out
+
+
+@pytest.fixture(scope="module")
+def sphere2500():
+    X, nrm = fibonacci_sphere(2500)
+    idx = knn(X, 31)
+    return X, nrm, idx
+
+
+# ----------------------------------------------------------------- kNN ----
+
+def test_knn_lattice_shells():
+    """Square lattice, spacing 1/8 (exact squared distances): the n nearest of
+    the centre node are whole distance shells, ordered by (d^2, index)."""
+    X, _ = planar_patch(9, spacing=0.125)
+    c = 40  # centre of the 9 x 9 lattice
+    # shells around the centre: d^2/h^2 = 0 (1), 1 (4), 2 (4), 4 (4), 5 (8)
+    for n, shell in [(1, 0), (5, 1), (9, 2), (13, 4), (21, 5)]:
+        idx = knn_bruteforce(X, n)[c]
+        assert idx[0] == c
+        d2 = np.sum((X[idx] - X[c]) ** 2, axis=1) / 0.125 ** 2
+        assert np.all(np.diff(d2) >= 0)
+        assert d2.max() == shell
+        # within a shell, indices ascend
+        for s in np.unique(d2):
+            sel = idx[d2 == s]
+            assert np.all(np.diff(sel) > 0)
+    # a tie at the cut: n = 7 takes the two lowest-index nodes of the d^2 = 2 shell
+    idx = knn_bruteforce(X, 7)[c]
+    diag = sorted([c - 10, c - 8, c + 8, c + 10])
+    assert list(idx[5:]) == diag[:2]
+
+
+def test_knn_tree_path_equals_bruteforce():
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((5000, 3))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    rows = rng.choice(5000, 200, replace=False)
+    a = knn(X, 40, rows=rows)
+    b = knn_bruteforce(X, 40)[rows]
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------- radial kernels ----
+
+@pytest.mark.parametrize("kernel", ["mq", "imq", "ga"])
+def test_psi_is_phi_prime_over_r(kernel):
+    eps = 1.7
+    r = np.linspace(0.05, 2.0, 40)
+    h = 1e-6
+    fd = (phi(kernel, eps, (r + h) ** 2) - phi(kernel, eps, (r - h) ** 2)) / (2 * h)
+    assert np.allclose(psi(kernel, eps, r * r) * r, fd, rtol=1e-7, atol=1e-9)
+
+
+def test_kernel_values_at_known_points():
+    # phi(0) = 1 for all three; mq(r=1, eps=1) = sqrt 2
+    for k in ("mq", "imq", "ga"):
+        assert phi(k, 3.0, 0.0) == 1.0
+    assert phi("mq", 1.0, 1.0) == math.sqrt(2.0)
+    assert phi("imq", 1.0, 3.0) == 0.5
+    assert phi("ga", 2.0, 0.25) == math.exp(-1.0)
+
+
+# ------------------------------------------------------ polynomial border ----
+
+def test_border_rank_by_surface():
+    X, _ = fibonacci_sphere(2500)
+    s = knn(X, 31, rows=[7])[0]
+    assert poly_border(X[s], 2)[0].shape[1] == 9      # x^2+y^2+z^2 = 1 on the sphere
+    assert poly_border(X[s], 1)[0].shape[1] == 4
+    assert poly_border(X[s], 0)[0].shape[1] == 1
+    P, _ = planar_patch(9, seed=1, jitter=0.3)
+    sp = knn(P, 31, rows=[40])[0]
+    assert poly_border(P[sp], 2)[0].shape[1] == 6     # z = 0: 4 monomials vanish
+    T, _ = jittered_torus(40, 120)
+    st = knn(T, 50, rows=[100])[0]
+    assert poly_border(T[st], 2)[0].shape[1] == 10
+    U = poly_border(X[s], 2)[0]
+    assert np.allclose(U.T @ U, np.eye(9), atol=1e-12)
+
+
+# --------------------------------------------------------------- weights ----
+
+def _rows(step=97):
+    return np.arange(0, 2500, step)
+
+
+def test_row_sums_vanish(sphere2500):
+    """Constants are reproduced and have zero surface gradient: L 1 = 0."""
+    X, nrm, idx = sphere2500
+    rows = _rows()
+    W = build_weights(X, nrm, idx, 4.0, rows=rows)   # kappa ~ 5e6
+    s = np.abs(W).sum(axis=1)
+    assert np.max(np.abs(W.sum(axis=1)) / s) < 1e-11
+
+
+def test_first_harmonics_exact_on_unit_sphere(sphere2500):
+    """x, y, z are degree-1 harmonics (Delta_S x = -2x) and their projected
+    gradients are quadratics reproduced by the degree-2 border, so the
+    discrete operator is exact on them."""
+    X, nrm, idx = sphere2500
+    rows = _rows()
+    W = build_weights(X, nrm, idx, 4.0, rows=rows)
+    s = np.abs(W).sum(axis=1)
+    for d in range(3):
+        lx = np.sum(W * X[idx[rows]][:, :, d], axis=1)
+        assert np.max(np.abs(lx + 2.0 * X[rows, d]) / s) < 1e-11
+
+
+def test_planar_quadratic_exact():
+    """On a plane the surface Laplacian is the 2-D Laplacian; degree-2 border
+    reproduces quadratics and their (linear) gradients exactly."""
+    P, nrm = planar_patch(11, spacing=0.1, seed=2, jitter=0.3)
+    idx = knn(P, 31, rows=[60])
+    s = idx[0]
+    w = stencil_weights(P[s], nrm[s], 3.0)
+    x, y = P[s, 0], P[s, 1]
+    q = 1.5 * x * x - 0.7 * x * y + 2.5 * y * y + 0.3 * x - 1.1 * y + 4.0
+    assert abs(w @ q - 2 * (1.5 + 2.5)) < 1e-6 * np.abs(w).sum() * 1e-2
+
+
+def test_normal_orientation_irrelevant(sphere2500):
+    X, nrm, idx = sphere2500
+    s = idx[11]
+    a = stencil_weights(X[s], nrm[s], 2.0)
+    b = stencil_weights(X[s], -nrm[s], 2.0)
+    assert np.array_equal(a, b)
+
+
+def test_rotation_translation_scale_invariance(sphere2500):
+    X, nrm, idx = sphere2500
+    s = idx[123]
+    eps = 4.0
+    w0 = stencil_weights(X[s], nrm[s], eps)
+    k = stencil_kappa(X[s], eps)
+    tol = max(1e-9, 0.5 * k * U64) * 4
+    Q, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((3, 3)))
+    w1 = stencil_weights(X[s] @ Q.T + np.array([0.3, -2.0, 1.0]), nrm[s] @ Q.T, eps)
+    assert np.linalg.norm(w1 - w0) / np.linalg.norm(w0) < tol
+    sc = 2.5
+    w2 = stencil_weights(sc * X[s], nrm[s], eps / sc)
+    assert np.linalg.norm(w2 * sc * sc - w0) / np.linalg.norm(w0) < tol
+
+
+def test_two_routes_agree(sphere2500):
+    X, nrm, idx = sphere2500
+    for i in (0, 500, 1700):
+        s = idx[i]
+        for eps in (4.0, 2.0):
+            a = stencil_weights(X[s], nrm[s], eps)
+            b = stencil_weights_row1(X[s], nrm[s], eps)
+            k = stencil_kappa(X[s], eps)
+            assert np.linalg.norm(a - b) / np.linalg.norm(a) < max(1e-9, 0.5 * k * U64)
+
+
+@pytest.mark.slow
+def test_against_60_digit_truth(sphere2500):
+    X, nrm, idx = sphere2500
+    for i, eps in ((3, 4.0), (1201, 2.0)):
+        s = idx[i]
+        wt = stencil_weights_mp(X[s], nrm[s], eps)
+        w = stencil_weights(X[s], nrm[s], eps)
+        k = stencil_kappa(X[s], eps)
+        assert np.linalg.norm(w - wt) / np.linalg.norm(wt) < max(1e-12, 0.25 * k * U64)
+        assert abs(wt.sum()) < 1e-14 * np.abs(wt).sum()
+
+
+def test_spherical_harmonic_eigenrelation_converges():
+    """Delta_S Y_l^m = -l(l+1) Y_l^m; at a fixed eps (condition number growing
+    with N, as in Sec. 6.1) the n = 31 error falls at high order in sqrt(N)
+    (the paper reports order four to five for n = 17 and 31)."""
+    errs = []
+    for N in (1000, 4000):
+        X, nrm = fibonacci_sphere(N)
+        idx = knn(X, 31)
+        W = build_weights(X, nrm, idx, 2.0)
+        L = assemble(idx, W)
+        Y = real_sph_harm(4, -2, X)
+        errs.append(np.linalg.norm(L @ Y + 20.0 * Y) / np.linalg.norm(20.0 * Y))
+    assert errs[0] < 1e-2
+    assert errs[1] < errs[0] / 16.0  # order >= 4 in sqrt(N) (measured 26x)
+
+
+def test_spectrum_left_half_plane():
+    """Sec. 5: stability needs Re(lambda) <= 0 for all eigenvalues of L_X."""
+    X, nrm = fibonacci_sphere(1000)
+    idx = knn(X, 31)
+    L = assemble(idx, build_weights(X, nrm, idx, 2.0 * math.sqrt(1000 / 2500.0))).toarray()
+    lam = np.linalg.eigvals(L)
+    rho = np.abs(lam).max()
+    assert lam.real.max() < 1e-9 * rho
+
+
+def test_sparsity_matches_paper_fraction():
+    g = golden()
+    assert abs(31 / 10000 - g["nnz_fraction_rbc_N10000_n31"]) < 1e-12
+    # printed to two decimals of a percent (0.615% shows as 0.62%)
+    assert abs(31 / 5041 - g["nnz_fraction_dtorus_N5041_n31"]) < 6e-5
+    X, nrm = fibonacci_sphere(5041)
+    idx = knn(X, 31, rows=np.arange(5041))
+    L = assemble(idx, np.ones(idx.shape))
+    assert L.nnz == 31 * 5041
+
+
+# ------------------------------------------------------ condition number ----
+
+def test_kappa_two_node_closed_form():
+    """n = 2, IMQ, constant border: A~ = [[1, a, 1], [a, 1, 1], [1, 1, 0]] has
+    eigenvalues 1 - a and ((1+a) +- sqrt((1+a)^2 + 8))/2."""
+    Xs = np.array([[0.0, 0.0, 0.0], [0.6, 0.0, 0.8]])
+    eps = 0.75
+    a = 1.0 / math.sqrt(1.0 + eps * eps * 1.0)
+    lam = [1 - a, ((1 + a) + math.sqrt((1 + a) ** 2 + 8)) / 2, ((1 + a) - math.sqrt((1 + a) ** 2 + 8)) / 2]
+    lam = np.abs(lam)
+    assert abs(stencil_kappa(Xs, eps, "imq", 0) - lam.max() / lam.min()) < 1e-12 * lam.max() / lam.min()
+
+
+def test_kappa2_of_diagonal():
+    assert kappa2(np.diag([3.0, -0.5, 2.0])) == 6.0
+
+
+def test_kappa_decreases_with_eps(sphere2500):
+    X, _, idx = sphere2500
+    s = idx[42]
+    ks = [stencil_kappa(X[s], e) for e in np.linspace(1.5, 8.0, 14)]
+    assert all(a > b for a, b in zip(ks, ks[1:]))
+
+
+def test_bisection_hits_target():
+    X, _ = fibonacci_sphere(10000)
+    s = knn(X, 50, rows=[17])[0]
+    kT = 1e12
+    eps, kap, ev, st = bisect_eps(X[s], kT)
+    assert st == 0
+    assert stencil_kappa(X[s], eps - 1e-4) > kT >= stencil_kappa(X[s], eps + 1e-4)
+    rho = math.sqrt(np.max(np.sum((X[s] - X[s[0]]) ** 2, axis=1)))
+    assert 0.4 < eps * rho < 0.8
+    assert abs(math.log(kap / kT)) < 0.01
+    assert 18 <= ev <= 30
+
+
+# --------------------------------------------------------------- stepper ----
+
+def test_rk4_one_step_is_taylor_quartic():
+    lam = -3.0
+    L = assemble(np.array([[0]]), np.array([[lam]]))
+    dt = 0.1
+    (y,) = rk4(L, [np.array([1.0])], [1.0], dt=dt, nsteps=1)
+    z = lam * dt
+    assert abs(y[0] - (1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24)) < 1e-15
+
+
+def test_heat_decay_on_sphere_against_exact(sphere2500):
+    """configs[0]-type run: u0 = Y_6^3 + 0.1 Y_2^1 decays as exp(-l(l+1)t).
+    The error is discretisation error (measured 1.98e-3 at t = 0.1)."""
+    X, nrm, idx = sphere2500
+    L = assemble(idx, build_weights(X, nrm, idx, 2.0))
+    u0 = real_sph_harm(6, 3, X) + 0.1 * real_sph_harm(2, 1, X)
+    (u,) = rk4(L, [u0], [1.0], dt=1e-4, nsteps=1000)
+    ue = math.exp(-42 * 0.1) * real_sph_harm(6, 3, X) + 0.1 * math.exp(-6 * 0.1) * real_sph_harm(2, 1, X)
+    err = np.linalg.norm(u - ue) / np.linalg.norm(ue)
+    assert err < 3e-3
+
+
+def test_schnakenberg_fixed_point_and_uniform_mode(sphere2500):
+    X, nrm, idx = sphere2500
+    prm = {"a": 0.1, "b": 0.9, "gamma": 50.0}
+    Ru, Rv = reaction("schnakenberg", [np.array([1.0]), np.array([0.9])], prm)
+    assert abs(Ru[0]) < 1e-14 and abs(Rv[0]) < 1e-14
+    L = assemble(idx, build_weights(X, nrm, idx, 4.0))
+    # a spatially uniform state stays uniform and follows the kinetics ODE
+    u0 = np.full(2500, 1.003)
+    v0 = np.full(2500, 0.897)
+    U, V = rk4(L, [u0, v0], [1.0, 10.0], "schnakenberg", prm, dt=1e-4, nsteps=50)
+    one = assemble(np.array([[0]]), np.array([[0.0]]))
+    u1, v1 = rk4(one, [u0[:1], v0[:1]], [1.0, 10.0], "schnakenberg", prm, dt=1e-4, nsteps=50)
+    assert np.max(np.abs(U - u1[0])) < 1e-9 and np.max(np.abs(V - v1[0])) < 1e-9
+
+
+def test_turing_model_equilibrium_from_table1():
+    """Sec. 7: with alpha = -gamma (Table 1), (0, 0) is an equilibrium; the
+    reaction is also odd-symmetric in (u, v) up to the quadratic tau2 terms."""
+    g = golden()
+    prm = {"alpha": g["turing_alpha"], "beta": g["turing_beta"], "gamma": g["turing_gamma"],
+           "tau1": g["turing_spots_tau1"], "tau2": g["turing_spots_tau2"]}
+    assert prm["alpha"] == -prm["gamma"]
+    Ru, Rv = reaction("turing", [np.zeros(1), np.zeros(1)], prm)
+    assert Ru[0] == 0.0 and Rv[0] == 0.0
+    # linearisation at 0 is [[alpha, 1], [gamma, beta]]: check by differences
+    h = 1e-7
+    Ru1, Rv1 = reaction("turing", [np.array([h]), np.zeros(1)], prm)
+    Ru2, Rv2 = reaction("turing", [np.zeros(1), np.array([h])], prm)
+    J = np.array([[Ru1[0], Ru2[0]], [Rv1[0], Rv2[0]]]) / h
+    assert np.allclose(J, [[prm["alpha"], 1.0], [prm["gamma"], prm["beta"]]], atol=1e-6)
+
+
+def test_ic_generators_are_seeded():
+    a = schnakenberg_ic(100)
+    b = schnakenberg_ic(100)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
