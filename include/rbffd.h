@@ -1,0 +1,175 @@
+/*
+ * rbffd.h -- C ABI of the RBF-FD surface-diffusion library for MI355X (gfx950).
+ *
+ * The library computes RBF-FD weights for the projected (extrinsic) surface
+ * Laplacian on scattered nodes with unit normals, and advances
+ * du_s/dt = D_s L_X u_s + R_s(u) with the sparse operator L_X.  It follows the
+ * paper "A Radial Basis Function (RBF)-Finite Difference (FD) Method for
+ * Diffusion and Reaction-Diffusion Equations on Surfaces" (Shankar, Wright,
+ * Kirby, Fogelson; arXiv:1404.0812): Sec. 4 (stencils, local interpolant,
+ * projected gradients, L_P and first-row weights), Sec. 5 (per-stencil shape
+ * parameter for a target condition number) and Sec. 4.2 (method of lines).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers owned by the caller, unless a
+ *    comment says "host".  The library never frees or keeps them.
+ *  - Every call is enqueued on the stream given to rbffd_create and returns
+ *    before the work completes; synchronise that stream before reading
+ *    outputs.  Outputs that are written must not alias inputs.
+ *  - Return value: 0 on success, a negative RBFFD_E* code on error.  On
+ *    error nothing has been enqueued and rbffd_last_error() holds a message.
+ *  - Node arrays are N x 3 row-major FP64 (x0 y0 z0 x1 y1 z1 ...).
+ *  - Stencil arrays are N x n row-major: row i lists node i first, then its
+ *    n-1 nearest neighbours by Euclidean distance in R^3, ascending by
+ *    (squared distance, node index); w[i*n + k] is the weight of node
+ *    idx[i*n + k] in the approximation of the surface Laplacian at node i.
+ *  - One context per stream; a context is not thread-safe.
+ */
+#ifndef RBFFD_H
+#define RBFFD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbffd_ctx_s* rbffd_ctx;
+typedef struct rbffd_op_s* rbffd_op;
+
+/* error codes */
+#define RBFFD_OK 0
+#define RBFFD_E_ARG (-1)      /* invalid argument (sizes, enum values, null pointer) */
+#define RBFFD_E_HIP (-2)      /* a HIP runtime call failed */
+#define RBFFD_E_NOMEM (-3)    /* device allocation of library scratch failed */
+#define RBFFD_E_UNSUPPORTED (-4) /* valid request outside what this build implements */
+
+/* radial kernels (Sec. 2) */
+#define RBFFD_KERNEL_MQ 0  /* sqrt(1 + (eps r)^2) */
+#define RBFFD_KERNEL_IMQ 1 /* 1 / sqrt(1 + (eps r)^2) -- the paper's choice */
+#define RBFFD_KERNEL_GA 2  /* exp(-(eps r)^2) */
+
+/* shape-parameter modes (Sec. 5) */
+#define RBFFD_EPS_FIXED 0   /* one eps for all stencils: opts.eps_fixed */
+#define RBFFD_EPS_GIVEN 1   /* per-stencil eps read from eps_in[N] */
+#define RBFFD_EPS_BISECT 2  /* per-stencil bisection on eps to kappa_2 = kappa_target */
+#define RBFFD_EPS_LEARNED 3 /* start from eps_in[N] (a prediction); keep it if
+                               kappa_2 lies in [band_lo, band_hi], else bisect */
+
+/* per-stencil status codes */
+#define RBFFD_ST_OK 0
+#define RBFFD_ST_FALLBACK 1   /* LEARNED: prediction outside the band, bisection used */
+#define RBFFD_ST_NO_BRACKET 2 /* bisection bracket could not be formed */
+#define RBFFD_ST_NONFINITE 3  /* non-finite entries in the local system */
+#define RBFFD_ST_SINGULAR 4   /* zero pivot in the tridiagonal solve */
+#define RBFFD_ST_DUPLICATE 5  /* two stencil nodes coincide */
+
+/* reaction terms for rbffd_step */
+#define RBFFD_REACT_NONE 0
+#define RBFFD_REACT_SCHNAKENBERG 1 /* params: a, b, gamma */
+#define RBFFD_REACT_TURING 2       /* params: alpha, beta, gamma, tau1, tau2 (eqs. turing1-2) */
+
+/* state precision for rbffd_step / rbffd_apply */
+#define RBFFD_F64 0
+#define RBFFD_F32 1
+
+typedef struct {
+    int32_t n;            /* stencil size including the centre, 2 <= n <= 128 */
+    int32_t kernel;       /* RBFFD_KERNEL_* */
+    int32_t poly_degree;  /* 0: the paper's constant border (ones); 1 or 2: monomials
+                             in (x - x_1)/rho reduced to an orthonormal basis of
+                             their numerical range (columns dropped below rank_tol) */
+    int32_t eps_mode;     /* RBFFD_EPS_* */
+    double eps_fixed;     /* FIXED mode */
+    double kappa_target;  /* BISECT/LEARNED: target 2-norm condition number */
+    double eps_tol;       /* bisection stops when hi - lo <= eps_tol (absolute, in eps) */
+    double bracket_lo;    /* initial bracket [bracket_lo, bracket_hi] / rho */
+    double bracket_hi;
+    double band_lo;       /* LEARNED acceptance band for kappa_2; also the band for */
+    double band_hi;       /*   band_stop */
+    double rank_tol;      /* relative drop tolerance for border columns */
+    int32_t band_stop;    /* BISECT: 1 = stop as soon as kappa_2 is inside the band */
+    int32_t max_expand;   /* bracket expansions allowed on each side */
+} rbffd_weight_opts;
+
+/* Fill opts with the defaults: n = 31, MQ, degree 2, FIXED eps 2, kappa_target
+ * 1e12, eps_tol 1e-4 (Sec. 5), bracket [0.05, 20]/rho, band [1e11, 1e13],
+ * rank_tol 1e-10, band_stop 0, max_expand 8.  opts is a HOST pointer. */
+void rbffd_default_opts(rbffd_weight_opts* opts);
+
+/* Create a context bound to `stream` (a hipStream_t; NULL = the null stream)
+ * on the current device.  *out is a HOST pointer that receives the handle. */
+int rbffd_create(rbffd_ctx* out, void* stream);
+int rbffd_destroy(rbffd_ctx ctx);
+/* Message of the last error on this context (static storage of the context). */
+const char* rbffd_last_error(rbffd_ctx ctx);
+
+/*
+ * Stencils (Sec. 4; Sec. 4.1 uses a k-d tree, this uses a uniform grid hash).
+ * xyz: N x 3 FP64.  idx: N x n int32 output in the layout described above.
+ * perm (nullable): N int32 output, the library's spatial order, perm[p] =
+ * caller index of the node at position p (cell-sorted, Morton order of cells).
+ * Errors: n < 1, n > N, n > 128, N > 2^31 - 1.
+ */
+int rbffd_knn(rbffd_ctx ctx, int64_t N, const double* xyz, int32_t n, int32_t* idx, int32_t* perm);
+
+/*
+ * Weights (Secs. 4 and 5).  xyz, nrm: N x 3 FP64 (normals need not be unit
+ * length or consistently oriented; only nu nu^T enters).  idx_in: N x n
+ * stencils; if NULL the call computes them first (rbffd_knn) and writes them
+ * to idx_out (which must then be non-NULL).  eps_in: N FP64 shape parameters
+ * for GIVEN/LEARNED modes (NULL otherwise).
+ * Outputs: w (N x n FP64), eps (N, nullable), kappa (N, nullable: kappa_2 of
+ * the bordered local matrix at the returned eps), status (N int32, nullable),
+ * nevals (N int32, nullable: number of kappa_2 evaluations of the stencil).
+ * Errors: as rbffd_knn; kernel/degree/mode out of range; n + border > 128.
+ */
+int rbffd_build_weights(rbffd_ctx ctx, int64_t N, const double* xyz, const double* nrm,
+                        const rbffd_weight_opts* opts, const int32_t* idx_in, const double* eps_in,
+                        int32_t* idx_out, double* w, double* eps, double* kappa, int32_t* status,
+                        int32_t* nevals);
+
+/*
+ * kappa_2 of every stencil's bordered local matrix at the given eps (Sec. 5,
+ * eq. target_cond): max|lambda| / min|lambda|.  Inputs as rbffd_build_weights;
+ * eps_in is required.  kappa: N FP64 output.
+ */
+int rbffd_kappa(rbffd_ctx ctx, int64_t N, const double* xyz, const rbffd_weight_opts* opts,
+                const int32_t* idx, const double* eps_in, double* kappa);
+
+/*
+ * Sparse operator L_X (Sec. 4: row k = weights of stencil k).  Built from
+ * caller-order idx/w (N x n); stored internally in ELL slot-major form in the
+ * spatial order `perm` (nullable: identity), in FP64 and, for FP32 stepping,
+ * as FP32 off-diagonal weights for the difference form
+ * sum_{j != i} w_ij (u_j - u_i).  *out is a HOST pointer.  The operator owns
+ * device memory freed by rbffd_op_destroy.
+ */
+int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_t* idx, const double* w,
+                    const int32_t* perm, rbffd_op* out);
+int rbffd_op_destroy(rbffd_op op);
+
+/*
+ * One operator application Lu = L_X u (caller order, FP64 in and out),
+ * computed in FP64 (plain form sum_j w_ij u_j) or FP32 (difference form).
+ */
+int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const double* u, double* Lu);
+
+/*
+ * Method of lines (Sec. 4.2, eq. kernel_mol) with classical RK4:
+ * du_s/dt = D[s] L_X u_s + R_s(u).  state: nspecies x N FP64, caller order,
+ * read and overwritten with the state after nsteps steps.  D: nspecies
+ * diffusivities (HOST).  params: reaction parameters (HOST, see
+ * RBFFD_REACT_*).  prec selects FP64 or FP32 state arithmetic (FP32 uses the
+ * difference form).  Steps run as a captured HIP graph of `graph_steps`
+ * steps (0 = library default), replayed as needed.
+ * Errors: nspecies not 1 or 2, a reaction needing 2 species given 1, dt <= 0.
+ */
+int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec,
+               const double* D, int32_t reaction, const double* params, double dt, int64_t nsteps,
+               int32_t graph_steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBFFD_H */

@@ -1,9 +1,10 @@
 """Stencil membership (Sec. 4): node x_1 plus its n-1 nearest neighbours.
 
 Distances are Euclidean in R^3 (straight-line, not along the surface).  The
-stencil size n counts the centre.  Ties are broken by the original node
-index, and the squared distance is formed as ((dx*dx + dy*dy) + dz*dz) in
-FP64 with no fused multiply-add, so that the order is exactly reproducible.
+stencil size n counts the centre, which always takes slot 0; the other n-1
+nodes are ascending by (squared distance, node index).  The squared distance
+is formed as ((dx*dx + dy*dy) + dz*dz) in FP64 with no fused multiply-add, so
+that the order is exactly reproducible.
 
 Parity pin: brute force on tiny inputs and exact-tie lattices (tests).
 """
@@ -21,10 +22,12 @@ def sqdist_rows(X: np.ndarray, i: int, cand: np.ndarray) -> np.ndarray:
     return (dx * dx + dy * dy) + dz * dz
 
 
-def _order(d2: np.ndarray, cand: np.ndarray, n: int) -> np.ndarray:
-    # ascending by (d2, index): lexsort sorts by the last key first
-    o = np.lexsort((cand, d2))
-    return cand[o[:n]]
+def _order(i: int, d2: np.ndarray, cand: np.ndarray, n: int) -> np.ndarray:
+    # centre first, then ascending by (d2, index); lexsort sorts by the last key first
+    keep = cand != i
+    c, d = cand[keep], d2[keep]
+    o = np.lexsort((c, d))
+    return np.concatenate([[i], c[o[:n - 1]]])
 
 
 def knn_bruteforce(X: np.ndarray, n: int) -> np.ndarray:
@@ -35,7 +38,7 @@ def knn_bruteforce(X: np.ndarray, n: int) -> np.ndarray:
     out = np.empty((N, n), dtype=np.int64)
     allidx = np.arange(N)
     for i in range(N):
-        out[i] = _order(sqdist_rows(X, i, allidx), allidx, n)
+        out[i] = _order(i, sqdist_rows(X, i, allidx), allidx, n)
     return out
 
 
@@ -57,7 +60,7 @@ def knn(X: np.ndarray, n: int, rows=None) -> np.ndarray:
         out = np.empty((len(rows), n), dtype=np.int64)
         allidx = np.arange(N)
         for t, i in enumerate(rows):
-            out[t] = _order(sqdist_rows(X, i, allidx), allidx, n)
+            out[t] = _order(i, sqdist_rows(X, i, allidx), allidx, n)
         return out
     tree = cKDTree(X)
     out = np.empty((len(rows), n), dtype=np.int64)
@@ -67,10 +70,11 @@ def knn(X: np.ndarray, n: int, rows=None) -> np.ndarray:
         c = np.asarray(cand[t])
         kk = k
         while True:
+            c = c[c != i]
             d2 = sqdist_rows(X, i, c)
             o = np.lexsort((c, d2))
-            if kk >= N or d2[o[n - 1]] < d2.max() * (1.0 - 1e-12):
-                out[t] = c[o[:n]]
+            if kk >= N or d2[o[n - 2]] < d2.max() * (1.0 - 1e-12):
+                out[t] = np.concatenate([[i], c[o[:n - 1]]])
                 break
             kk = min(N, 2 * kk)
             _, c = tree.query(X[i], k=kk)

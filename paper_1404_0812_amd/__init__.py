@@ -1,0 +1,224 @@
+"""RBF-FD surface diffusion on MI355X: Python binding of librbffd.so.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Arrays are torch CUDA tensors (device memory);
+results come back as new tensors.  Each Context owns a HIP stream at the
+default priority; calls order themselves after the caller's current stream
+and make it wait for their results.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+KERNELS = {"mq": 0, "imq": 1, "ga": 2}
+EPS_MODES = {"fixed": 0, "given": 1, "bisect": 2, "learned": 3}
+REACTIONS = {"none": 0, "schnakenberg": 1, "turing": 2}
+PRECS = {"f64": 0, "f32": 1}
+
+ST_OK, ST_FALLBACK, ST_NO_BRACKET, ST_NONFINITE, ST_SINGULAR, ST_DUPLICATE = range(6)
+
+
+class RbffdError(RuntimeError):
+    pass
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    return t.to(dtype).contiguous()
+
+
+class Context:
+    """A library context bound to its own HIP stream on the current device."""
+
+    def __init__(self, device=None):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.rbffd_create(ctypes.byref(h), ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise RbffdError(f"rbffd_create failed ({rc})")
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                self.lib.rbffd_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def check(self, rc):
+        if rc != 0:
+            msg = self.lib.rbffd_last_error(self.h)
+            raise RbffdError(f"rbffd error {rc}: {msg.decode() if msg else ''}")
+
+    def enter(self, *tensors):
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        for t in tensors:
+            if t is not None:
+                t.record_stream(self.stream)
+
+    def leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+
+_DEFAULT = {}
+
+
+def default_context():
+    dev = torch.cuda.current_device()
+    if dev not in _DEFAULT:
+        _DEFAULT[dev] = Context(dev)
+    return _DEFAULT[dev]
+
+
+def default_opts():
+    o = _lib.WeightOpts()
+    _lib.load().rbffd_default_opts(ctypes.byref(o))
+    return o
+
+
+def make_opts(n, kernel="mq", degree=2, eps_mode="fixed", eps=2.0, kappa_target=1e12, eps_tol=1e-4,
+              bracket=(0.05, 20.0), band=(1e11, 1e13), rank_tol=1e-10, band_stop=False, max_expand=8):
+    o = default_opts()
+    o.n = int(n)
+    o.kernel = KERNELS[kernel]
+    o.poly_degree = int(degree)
+    o.eps_mode = EPS_MODES[eps_mode]
+    o.eps_fixed = float(eps)
+    o.kappa_target = float(kappa_target)
+    o.eps_tol = float(eps_tol)
+    o.bracket_lo, o.bracket_hi = float(bracket[0]), float(bracket[1])
+    o.band_lo, o.band_hi = float(band[0]), float(band[1])
+    o.rank_tol = float(rank_tol)
+    o.band_stop = 1 if band_stop else 0
+    o.max_expand = int(max_expand)
+    return o
+
+
+def knn(xyz, n, ctx=None, with_perm=True):
+    """Stencils (N x n int32, centre first) and the spatial order perm (N int32)."""
+    ctx = ctx or default_context()
+    xyz = _dev(xyz, torch.float64, "xyz")
+    N = xyz.shape[0]
+    idx = torch.empty((N, n), dtype=torch.int32, device=xyz.device)
+    perm = torch.empty(N, dtype=torch.int32, device=xyz.device) if with_perm else None
+    ctx.enter(xyz, idx, perm)
+    ctx.check(ctx.lib.rbffd_knn(ctx.h, N, _ptr(xyz), int(n), _ptr(idx), _ptr(perm)))
+    ctx.leave()
+    return idx, perm
+
+
+@dataclass
+class Weights:
+    idx: torch.Tensor
+    w: torch.Tensor
+    eps: torch.Tensor
+    kappa: torch.Tensor
+    status: torch.Tensor
+    nevals: torch.Tensor
+
+
+def build_weights(xyz, nrm, n, idx=None, eps_in=None, ctx=None, **kw):
+    """RBF-FD weights of the projected surface Laplacian (see make_opts for keywords)."""
+    ctx = ctx or default_context()
+    o = make_opts(n, **kw)
+    xyz = _dev(xyz, torch.float64, "xyz")
+    nrm = _dev(nrm, torch.float64, "nrm")
+    N = xyz.shape[0]
+    dev = xyz.device
+    idx_in = _dev(idx, torch.int32, "idx") if idx is not None else None
+    eps_t = _dev(eps_in, torch.float64, "eps_in") if eps_in is not None else None
+    idx_out = idx_in if idx_in is not None else torch.empty((N, n), dtype=torch.int32, device=dev)
+    w = torch.empty((N, n), dtype=torch.float64, device=dev)
+    eps = torch.empty(N, dtype=torch.float64, device=dev)
+    kap = torch.empty(N, dtype=torch.float64, device=dev)
+    st = torch.empty(N, dtype=torch.int32, device=dev)
+    ne = torch.empty(N, dtype=torch.int32, device=dev)
+    ctx.enter(xyz, nrm, idx_in, eps_t, idx_out, w, eps, kap, st, ne)
+    ctx.check(ctx.lib.rbffd_build_weights(ctx.h, N, _ptr(xyz), _ptr(nrm), ctypes.byref(o), _ptr(idx_in),
+                                          _ptr(eps_t), _ptr(idx_out) if idx_in is None else ctypes.c_void_p(0),
+                                          _ptr(w), _ptr(eps), _ptr(kap), _ptr(st), _ptr(ne)))
+    ctx.leave()
+    return Weights(idx_out, w, eps, kap, st, ne)
+
+
+def kappa(xyz, idx, eps_in, n=None, ctx=None, **kw):
+    """kappa_2 of each stencil's bordered local matrix at eps_in."""
+    ctx = ctx or default_context()
+    idx = _dev(idx, torch.int32, "idx")
+    n = idx.shape[1] if n is None else n
+    o = make_opts(n, **kw)
+    xyz = _dev(xyz, torch.float64, "xyz")
+    eps_t = _dev(eps_in, torch.float64, "eps_in")
+    N = xyz.shape[0]
+    out = torch.empty(N, dtype=torch.float64, device=xyz.device)
+    ctx.enter(xyz, idx, eps_t, out)
+    ctx.check(ctx.lib.rbffd_kappa(ctx.h, N, _ptr(xyz), ctypes.byref(o), _ptr(idx), _ptr(eps_t), _ptr(out)))
+    ctx.leave()
+    return out
+
+
+class Operator:
+    """Sparse L_X built from caller-order stencils and weights."""
+
+    def __init__(self, idx, w, perm=None, ctx=None):
+        self.ctx = ctx or default_context()
+        idx = _dev(idx, torch.int32, "idx")
+        w = _dev(w, torch.float64, "w")
+        perm = _dev(perm, torch.int32, "perm") if perm is not None else None
+        self.N, self.n = idx.shape
+        h = ctypes.c_void_p()
+        self.ctx.enter(idx, w, perm)
+        self.ctx.check(self.ctx.lib.rbffd_op_create(self.ctx.h, self.N, self.n, _ptr(idx), _ptr(w), _ptr(perm),
+                                                    ctypes.byref(h)))
+        self.ctx.leave()
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rbffd_op_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, u, prec="f64"):
+        u = _dev(u, torch.float64, "u")
+        out = torch.empty_like(u)
+        self.ctx.enter(u, out)
+        self.ctx.check(self.ctx.lib.rbffd_apply(self.ctx.h, self.h, PRECS[prec], _ptr(u), _ptr(out)))
+        self.ctx.leave()
+        return out
+
+    def step(self, state, dt, nsteps, prec="f64", D=(1.0,), reaction="none", params=(), graph_steps=0):
+        """Advance state (S x N float64, S = 1 or 2) by nsteps RK4 steps; returns the new state."""
+        st = _dev(state, torch.float64, "state").clone()
+        if st.dim() == 1:
+            st = st.unsqueeze(0)
+        S = st.shape[0]
+        Darr = (ctypes.c_double * max(2, len(D)))(*[float(x) for x in D])
+        prm = (ctypes.c_double * 5)(*([float(x) for x in params] + [0.0] * (5 - len(params))))
+        self.ctx.enter(st)
+        self.ctx.check(self.ctx.lib.rbffd_step(self.ctx.h, self.h, S, _ptr(st), PRECS[prec], Darr,
+                                               REACTIONS[reaction], prm, float(dt), int(nsteps), int(graph_steps)))
+        self.ctx.leave()
+        return st

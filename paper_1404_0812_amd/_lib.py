@@ -1,0 +1,72 @@
+"""ctypes declarations of librbffd.so (the C ABI in include/rbffd.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbffd.so")
+
+c_int32 = ctypes.c_int32
+c_int64 = ctypes.c_int64
+c_double = ctypes.c_double
+c_void_p = ctypes.c_void_p
+
+
+class WeightOpts(ctypes.Structure):
+    _fields_ = [
+        ("n", c_int32),
+        ("kernel", c_int32),
+        ("poly_degree", c_int32),
+        ("eps_mode", c_int32),
+        ("eps_fixed", c_double),
+        ("kappa_target", c_double),
+        ("eps_tol", c_double),
+        ("bracket_lo", c_double),
+        ("bracket_hi", c_double),
+        ("band_lo", c_double),
+        ("band_hi", c_double),
+        ("rank_tol", c_double),
+        ("band_stop", c_int32),
+        ("max_expand", c_int32),
+    ]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "rbffd_default_opts": (None, [ctypes.POINTER(WeightOpts)]),
+    "rbffd_create": (c_int32, [ctypes.POINTER(c_void_p), c_void_p]),
+    "rbffd_destroy": (c_int32, [c_void_p]),
+    "rbffd_last_error": (ctypes.c_char_p, [c_void_p]),
+    "rbffd_knn": (c_int32, [c_void_p, c_int64, c_void_p, c_int32, c_void_p, c_void_p]),
+    "rbffd_build_weights": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, ctypes.POINTER(WeightOpts),
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]),
+    "rbffd_kappa": (c_int32, [c_void_p, c_int64, c_void_p, ctypes.POINTER(WeightOpts), c_void_p, c_void_p,
+                              c_void_p]),
+    "rbffd_op_create": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p,
+                                  ctypes.POINTER(c_void_p)]),
+    "rbffd_op_destroy": (c_int32, [c_void_p]),
+    "rbffd_apply": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "rbffd_step": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double), c_int32,
+                             ctypes.POINTER(c_double), c_double, c_int64, c_int32]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load librbffd.so; raises if it has not been built (no fallback exists)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1404_0812_amd.build` "
+                "(there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB

@@ -1,0 +1,431 @@
+// Sparse operator L_X and the method-of-lines time stepper (Sec. 4.2,
+// eq. kernel_mol): du_s/dt = D_s L_X u_s + R_s(u), classical RK4.
+//
+// Layout: ELL, slot-major (slot k of all rows contiguous), rows in the
+// library's spatial order, so that the loads of the weights and indices are
+// coalesced across a wavefront and the gathered neighbour values are close in
+// memory.  Every row has exactly n entries (Sec. 4), so there is no padding.
+// FP64 state uses the plain form sum_j w_ij u_j over all n slots.  FP32 state
+// uses the difference form sum_{j != i} w_ij (u_j - u_i) with FP32 weights;
+// it equals L u because the rows of L_X sum to zero (constants are
+// reproduced), and it keeps L 1 = 0 exact in FP32.
+//
+// One RK4 stage is one kernel: it applies L to the stage input of every
+// species with one read of the row, adds the reaction, and writes the next
+// stage input and the RK accumulator; stage 4 writes the new state.  The
+// steps are captured in a HIP graph and replayed.
+#include "common.h"
+
+#include <cstring>
+
+namespace {
+
+constexpr int BLK = 256;
+
+__global__ void k_inverse_perm(int64_t N, const int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < N) iperm[perm ? perm[p] : p] = (int32_t)p;
+}
+
+__global__ void k_build_ell(int64_t N, int n, const int32_t* __restrict__ idx, const double* __restrict__ w,
+                            const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
+                            int32_t* __restrict__ ell_idx64, double* __restrict__ ell_w64,
+                            int32_t* __restrict__ ell_idx, float* __restrict__ ell_w32) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    int64_t i = perm ? perm[p] : p;
+    for (int k = 0; k < n; ++k) {
+        int j = iperm[idx[i * n + k]];
+        double wk = w[i * n + k];
+        ell_idx64[(int64_t)k * N + p] = j;
+        ell_w64[(int64_t)k * N + p] = wk;
+        if (k > 0) {
+            ell_idx[(int64_t)(k - 1) * N + p] = j;
+            ell_w32[(int64_t)(k - 1) * N + p] = (float)wk;
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_load_state(int64_t N, int S, const double* __restrict__ in, const int32_t* __restrict__ perm,
+                             T* __restrict__ out) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    int64_t i = perm ? perm[p] : p;
+    for (int s = 0; s < S; ++s) out[s * N + p] = (T)in[s * N + i];
+}
+
+template <typename T>
+__global__ void k_store_state(int64_t N, int S, const T* __restrict__ in, const int32_t* __restrict__ perm,
+                              double* __restrict__ out) {
+    int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    int64_t i = perm ? perm[p] : p;
+    for (int s = 0; s < S; ++s) out[s * N + i] = (double)in[s * N + p];
+}
+
+struct ReactParams {
+    double p[5];
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void reaction(const T (&y)[2], T (&r)[2], const ReactParams& rp) {
+    if (R == RBFFD_REACT_SCHNAKENBERG) {
+        const T a = (T)rp.p[0], b = (T)rp.p[1], g = (T)rp.p[2];
+        const T u2v = y[0] * y[0] * y[1];
+        r[0] = g * (a - y[0] + u2v);
+        r[1] = g * (b - u2v);
+    } else if (R == RBFFD_REACT_TURING) {
+        const T al = (T)rp.p[0], be = (T)rp.p[1], ga = (T)rp.p[2], t1 = (T)rp.p[3], t2 = (T)rp.p[4];
+        const T u = y[0], v = y[1];
+        r[0] = al * u * ((T)1 - t1 * v * v) + v * ((T)1 - t2 * u);
+        r[1] = be * v * ((T)1 + al * t1 / be * u * v) + u * (ga + t2 * v);
+    } else {
+        r[0] = (T)0;
+        r[1] = (T)0;
+    }
+}
+
+struct StageArgs {
+    int64_t N;
+    int nslots;       // slots read per row (n-1 for FP32 difference form, n for FP64)
+    double D[2];
+    double dt;
+    ReactParams rp;
+};
+
+// L applied to the stage input Y (S species), FP32 difference form
+template <int S>
+__device__ __forceinline__ void apply_rows_f32(const StageArgs& a, const int32_t* __restrict__ idx,
+                                               const float* __restrict__ w, const float* __restrict__ Y, int64_t p,
+                                               const float (&yi)[2], float (&acc)[2]) {
+    const int64_t N = a.N;
+    float s0 = 0.f, s1 = 0.f, t0 = 0.f, t1 = 0.f;
+    int k = 0;
+    for (; k + 2 <= a.nslots; k += 2) {
+        const int j0 = __builtin_nontemporal_load(idx + (int64_t)k * N + p);
+        const int j1 = __builtin_nontemporal_load(idx + (int64_t)(k + 1) * N + p);
+        const float w0 = __builtin_nontemporal_load(w + (int64_t)k * N + p);
+        const float w1 = __builtin_nontemporal_load(w + (int64_t)(k + 1) * N + p);
+        s0 = fmaf(w0, Y[j0] - yi[0], s0);
+        s1 = fmaf(w1, Y[j1] - yi[0], s1);
+        if (S == 2) {
+            t0 = fmaf(w0, Y[N + j0] - yi[1], t0);
+            t1 = fmaf(w1, Y[N + j1] - yi[1], t1);
+        }
+    }
+    if (k < a.nslots) {
+        const int j0 = __builtin_nontemporal_load(idx + (int64_t)k * N + p);
+        const float w0 = __builtin_nontemporal_load(w + (int64_t)k * N + p);
+        s0 = fmaf(w0, Y[j0] - yi[0], s0);
+        if (S == 2) t0 = fmaf(w0, Y[N + j0] - yi[1], t0);
+    }
+    acc[0] = s0 + s1;
+    acc[1] = t0 + t1;
+}
+
+// FP64 plain form over all n slots, in slot order
+template <int S>
+__device__ __forceinline__ void apply_rows_f64(const StageArgs& a, const int32_t* __restrict__ idx,
+                                               const double* __restrict__ w, const double* __restrict__ Y,
+                                               int64_t p, double (&acc)[2]) {
+    const int64_t N = a.N;
+    double s0 = 0.0, t0 = 0.0;
+    for (int k = 0; k < a.nslots; ++k) {
+        const int j = idx[(int64_t)k * N + p];
+        const double wk = w[(int64_t)k * N + p];
+        s0 = fma(wk, Y[j], s0);
+        if (S == 2) t0 = fma(wk, Y[N + j], t0);
+    }
+    acc[0] = s0;
+    acc[1] = t0;
+}
+
+// RK4 stage `st` (0..3).  Y: stage input; U: state at the start of the step;
+// ACC: accumulator; YN: next stage input (stages 0-2) -- stage 3 updates U.
+template <typename T, int S, int R, int ST>
+__global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* __restrict__ idx,
+                                                   const T* __restrict__ w, const T* __restrict__ Y,
+                                                   T* __restrict__ U, T* __restrict__ ACC, T* __restrict__ YN) {
+    const int64_t p = blockIdx.x * (int64_t)BLK + threadIdx.x;
+    const int64_t N = a.N;
+    if (p >= N) return;
+    T yi[2] = {Y[p], S == 2 ? Y[N + p] : (T)0};
+    T lap[2];
+    if constexpr (sizeof(T) == 4) {
+        apply_rows_f32<S>(a, idx, (const float*)w, (const float*)Y, p, yi, lap);
+    } else {
+        apply_rows_f64<S>(a, idx, (const double*)w, (const double*)Y, p, lap);
+    }
+    T r[2];
+    reaction<T, R>(yi, r, a.rp);
+    T k[2];
+    k[0] = (T)a.D[0] * lap[0] + r[0];
+    k[1] = (T)a.D[1] * lap[1] + r[1];
+    const T dt = (T)a.dt;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int64_t q = s * N + p;
+        if (ST == 0) {
+            ACC[q] = k[s];
+            YN[q] = U[q] + (T)0.5 * dt * k[s];
+        } else if (ST == 1) {
+            ACC[q] = ACC[q] + (T)2 * k[s];
+            YN[q] = U[q] + (T)0.5 * dt * k[s];
+        } else if (ST == 2) {
+            ACC[q] = ACC[q] + (T)2 * k[s];
+            YN[q] = U[q] + dt * k[s];
+        } else {
+            U[q] = U[q] + dt / (T)6 * (ACC[q] + k[s]);
+        }
+    }
+}
+
+// one operator application (stage-free): out = L y (reaction-free, D = 1)
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_apply(StageArgs a, const int32_t* __restrict__ idx, const T* __restrict__ w,
+                                               const T* __restrict__ Y, T* __restrict__ out) {
+    const int64_t p = blockIdx.x * (int64_t)BLK + threadIdx.x;
+    if (p >= a.N) return;
+    T yi[2] = {Y[p], (T)0};
+    T lap[2];
+    if constexpr (sizeof(T) == 4) {
+        apply_rows_f32<1>(a, idx, (const float*)w, (const float*)Y, p, yi, lap);
+    } else {
+        apply_rows_f64<1>(a, idx, (const double*)w, (const double*)Y, p, lap);
+    }
+    out[p] = lap[0];
+}
+
+template <typename T, int S, int R>
+void enqueue_step(hipStream_t st, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC, T* Y1, T* Y2) {
+    const dim3 g((unsigned)((a.N + BLK - 1) / BLK)), b(BLK);
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 0>), g, b, 0, st, a, idx, w, U, U, ACC, Y1);
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 1>), g, b, 0, st, a, idx, w, Y1, U, ACC, Y2);
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 2>), g, b, 0, st, a, idx, w, Y2, U, ACC, Y1);
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 3>), g, b, 0, st, a, idx, w, Y1, U, ACC, nullptr);
+}
+
+template <typename T>
+void enqueue_steps_t(hipStream_t st, int S, int R, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC,
+                     T* Y1, T* Y2, int64_t steps) {
+    for (int64_t i = 0; i < steps; ++i) {
+        if (S == 1) {
+            enqueue_step<T, 1, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2);
+        } else if (R == RBFFD_REACT_SCHNAKENBERG) {
+            enqueue_step<T, 2, RBFFD_REACT_SCHNAKENBERG>(st, a, idx, w, U, ACC, Y1, Y2);
+        } else if (R == RBFFD_REACT_TURING) {
+            enqueue_step<T, 2, RBFFD_REACT_TURING>(st, a, idx, w, U, ACC, Y1, Y2);
+        } else {
+            enqueue_step<T, 2, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2);
+        }
+    }
+}
+
+int ensure_work(rbffd_op op) {
+    // 4 buffers (U, ACC, Y1, Y2) x 2 species x FP64
+    size_t need = 4 * 2 * (size_t)op->N * sizeof(double);
+    if (op->work_bytes >= need) return RBFFD_OK;
+    if (op->work) {
+        (void)hipStreamSynchronize(op->ctx->stream);
+        (void)hipFree(op->work);
+        op->work = nullptr;
+    }
+    if (hipMalloc(&op->work, need) != hipSuccess) {
+        op->work = nullptr;
+        return set_error(op->ctx, RBFFD_E_NOMEM, "cannot allocate %zu bytes of state", need);
+    }
+    op->work_bytes = need;
+    return RBFFD_OK;
+}
+
+void reset_graph(rbffd_op op) {
+    if (op->graph) {
+        (void)hipGraphExecDestroy(op->graph);
+        op->graph = nullptr;
+    }
+    op->graph_key_species = -1;
+}
+
+}  // namespace
+
+extern "C" int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_t* idx, const double* w,
+                               const int32_t* perm, rbffd_op* out) {
+    if (!ctx || !out) return RBFFD_E_ARG;
+    if (N <= 0 || N > 0x7fffffffLL) return set_error(ctx, RBFFD_E_ARG, "N out of range");
+    if (n < 2 || n > 128 || n > N) return set_error(ctx, RBFFD_E_ARG, "stencil size n=%d invalid", n);
+    if (!idx || !w) return set_error(ctx, RBFFD_E_ARG, "null pointer");
+    rbffd_op op = new (std::nothrow) rbffd_op_s();
+    if (!op) return set_error(ctx, RBFFD_E_NOMEM, "host allocation failed");
+    op->ctx = ctx;
+    op->N = N;
+    op->n = n;
+    const size_t Nn = (size_t)N * n, Nm = (size_t)N * (n - 1);
+    bool ok = hipMalloc(&op->ell_idx64, Nn * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&op->ell_w64, Nn * sizeof(double)) == hipSuccess &&
+              hipMalloc(&op->ell_idx, Nm * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&op->ell_w32, Nm * sizeof(float)) == hipSuccess &&
+              hipMalloc(&op->perm, (size_t)N * sizeof(int32_t)) == hipSuccess;
+    int32_t* iperm = nullptr;
+    ok = ok && hipMalloc(&iperm, (size_t)N * sizeof(int32_t)) == hipSuccess;
+    if (!ok) {
+        rbffd_op_destroy(op);
+        if (iperm) (void)hipFree(iperm);
+        return set_error(ctx, RBFFD_E_NOMEM, "operator allocation failed");
+    }
+    hipStream_t st = ctx->stream;
+    const dim3 g((unsigned)((N + BLK - 1) / BLK)), b(BLK);
+    hipLaunchKernelGGL(k_inverse_perm, g, b, 0, st, N, perm, iperm);
+    hipLaunchKernelGGL(k_build_ell, g, b, 0, st, N, n, idx, w, perm, iperm, op->ell_idx64, op->ell_w64, op->ell_idx,
+                       op->ell_w32);
+    if (perm) {
+        (void)hipMemcpyAsync(op->perm, perm, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+    } else {
+        (void)hipFree(op->perm);
+        op->perm = nullptr;
+    }
+    hipError_t e = hipGetLastError();
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(iperm);
+    if (e != hipSuccess) {
+        rbffd_op_destroy(op);
+        return set_error(ctx, RBFFD_E_HIP, "operator build failed: %s", hipGetErrorString(e));
+    }
+    *out = op;
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_op_destroy(rbffd_op op) {
+    if (!op) return RBFFD_E_ARG;
+    if (op->ctx) (void)hipStreamSynchronize(op->ctx->stream);
+    reset_graph(op);
+    if (op->ell_idx64) (void)hipFree(op->ell_idx64);
+    if (op->ell_w64) (void)hipFree(op->ell_w64);
+    if (op->ell_idx) (void)hipFree(op->ell_idx);
+    if (op->ell_w32) (void)hipFree(op->ell_w32);
+    if (op->perm) (void)hipFree(op->perm);
+    if (op->work) (void)hipFree(op->work);
+    delete op;
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const double* u, double* Lu) {
+    if (!ctx || !op || !u || !Lu) return set_error(ctx, RBFFD_E_ARG, "null argument");
+    if (prec != RBFFD_F64 && prec != RBFFD_F32) return set_error(ctx, RBFFD_E_ARG, "prec must be F64 or F32");
+    op->ctx = ctx;
+    int rc = ensure_work(op);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    const int64_t N = op->N;
+    const dim3 g((unsigned)((N + BLK - 1) / BLK)), b(BLK);
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.N = N;
+    if (prec == RBFFD_F64) {
+        double* Y = (double*)op->work;
+        double* out = Y + N;
+        a.nslots = op->n;
+        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, N, 1, u, op->perm, Y);
+        hipLaunchKernelGGL(k_apply<double>, g, b, 0, st, a, op->ell_idx64, op->ell_w64, Y, out);
+        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, N, 1, out, op->perm, Lu);
+    } else {
+        float* Y = (float*)op->work;
+        float* out = Y + N;
+        a.nslots = op->n - 1;
+        hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, N, 1, u, op->perm, Y);
+        hipLaunchKernelGGL(k_apply<float>, g, b, 0, st, a, op->ell_idx, op->ell_w32, Y, out);
+        hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, N, 1, out, op->perm, Lu);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec, const double* D,
+                          int32_t reaction, const double* params, double dt, int64_t nsteps, int32_t graph_steps) {
+    if (!ctx || !op || !state || !D) return set_error(ctx, RBFFD_E_ARG, "null argument");
+    if (nspecies != 1 && nspecies != 2) return set_error(ctx, RBFFD_E_ARG, "nspecies must be 1 or 2");
+    if (prec != RBFFD_F64 && prec != RBFFD_F32) return set_error(ctx, RBFFD_E_ARG, "prec must be F64 or F32");
+    if (reaction < 0 || reaction > 2) return set_error(ctx, RBFFD_E_ARG, "unknown reaction %d", reaction);
+    if (reaction != RBFFD_REACT_NONE && nspecies != 2)
+        return set_error(ctx, RBFFD_E_ARG, "reaction needs two species");
+    if (reaction != RBFFD_REACT_NONE && !params) return set_error(ctx, RBFFD_E_ARG, "reaction params required");
+    if (!(dt > 0.0)) return set_error(ctx, RBFFD_E_ARG, "dt must be > 0");
+    if (nsteps < 0) return set_error(ctx, RBFFD_E_ARG, "nsteps must be >= 0");
+    if (graph_steps < 0) return set_error(ctx, RBFFD_E_ARG, "graph_steps must be >= 0");
+    op->ctx = ctx;
+    int rc = ensure_work(op);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    const int64_t N = op->N;
+    const dim3 g((unsigned)((N + BLK - 1) / BLK)), b(BLK);
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.N = N;
+    a.D[0] = D[0];
+    a.D[1] = nspecies == 2 ? D[1] : 0.0;
+    a.dt = dt;
+    const int np = reaction == RBFFD_REACT_SCHNAKENBERG ? 3 : (reaction == RBFFD_REACT_TURING ? 5 : 0);
+    for (int i = 0; i < np; ++i) a.rp.p[i] = params[i];
+    const int G = graph_steps > 0 ? graph_steps : 50;
+    const size_t esz = prec == RBFFD_F64 ? sizeof(double) : sizeof(float);
+    char* base = (char*)op->work;
+    void* U = base;
+    void* ACC = base + 2 * N * esz;
+    void* Y1 = base + 4 * N * esz;
+    void* Y2 = base + 6 * N * esz;
+    const int32_t* idx = prec == RBFFD_F64 ? op->ell_idx64 : op->ell_idx;
+    const void* w = prec == RBFFD_F64 ? (const void*)op->ell_w64 : (const void*)op->ell_w32;
+    a.nslots = prec == RBFFD_F64 ? op->n : op->n - 1;
+    if (prec == RBFFD_F64)
+        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, N, nspecies, state, op->perm, (double*)U);
+    else
+        hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, N, nspecies, state, op->perm, (float*)U);
+    HIP_TRY(ctx, hipGetLastError());
+
+    auto enqueue = [&](hipStream_t s, int64_t steps) {
+        if (prec == RBFFD_F64)
+            enqueue_steps_t<double>(s, nspecies, reaction, a, idx, (const double*)w, (double*)U, (double*)ACC,
+                                    (double*)Y1, (double*)Y2, steps);
+        else
+            enqueue_steps_t<float>(s, nspecies, reaction, a, idx, (const float*)w, (float*)U, (float*)ACC,
+                                   (float*)Y1, (float*)Y2, steps);
+    };
+    const int64_t reps = nsteps / G;
+    const int64_t rest = nsteps % G;
+    if (reps > 0) {
+        bool same = op->graph && op->graph_key_species == nspecies && op->graph_key_prec == prec &&
+                    op->graph_key_react == reaction && op->graph_key_steps == G && op->graph_key_dt == dt &&
+                    op->graph_key_D[0] == a.D[0] && op->graph_key_D[1] == a.D[1] &&
+                    std::memcmp(op->graph_key_params, a.rp.p, sizeof(a.rp.p)) == 0;
+        if (!same) {
+            reset_graph(op);
+            hipGraph_t graph;
+            HIP_TRY(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            enqueue(st, G);
+            hipError_t ce = hipStreamEndCapture(st, &graph);
+            if (ce != hipSuccess) return set_error(ctx, RBFFD_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+            hipError_t ie = hipGraphInstantiate(&op->graph, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                op->graph = nullptr;
+                return set_error(ctx, RBFFD_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
+            }
+            op->graph_key_species = nspecies;
+            op->graph_key_prec = prec;
+            op->graph_key_react = reaction;
+            op->graph_key_steps = G;
+            op->graph_key_dt = dt;
+            op->graph_key_D[0] = a.D[0];
+            op->graph_key_D[1] = a.D[1];
+            std::memcpy(op->graph_key_params, a.rp.p, sizeof(a.rp.p));
+        }
+        for (int64_t r = 0; r < reps; ++r) HIP_TRY(ctx, hipGraphLaunch(op->graph, st));
+    }
+    if (rest > 0) enqueue(st, rest);
+    if (prec == RBFFD_F64)
+        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, N, nspecies, (const double*)U, op->perm, state);
+    else
+        hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, N, nspecies, (const float*)U, op->perm, state);
+    HIP_TRY(ctx, hipGetLastError());
+    return RBFFD_OK;
+}

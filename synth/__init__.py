@@ -12,6 +12,7 @@ from .nodes import (  # noqa: F401
     blob,
     planar_patch,
     surface_batch,
+    cached,
 )
 from .fields import (  # noqa: F401
     real_sph_harm,

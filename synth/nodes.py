@@ -24,6 +24,7 @@ __all__ = [
     "blob",
     "planar_patch",
     "surface_batch",
+    "cached",
 ]
 
 
@@ -114,20 +115,22 @@ def blob(N: int, seed: int = 4, ncentres: int = 8, s2: float = 0.3, level: float
         P = rng.uniform(lo, hi, size=(chunk, 3))
         f, _ = _blob_f_grad(P, C, s2)
         P = P[np.abs(f - level) < 0.25]
+        done = np.zeros(len(P), dtype=bool)
         for _ in range(60):
-            f, g = _blob_f_grad(P, C, s2)
+            act = np.flatnonzero(~done)
+            if len(act) == 0:
+                break
+            Q = P[act]
+            f, g = _blob_f_grad(Q, C, s2)
             gg = np.sum(g * g, axis=1)
-            ok = gg > 1e-8
-            P = P[ok]
-            f, g, gg = f[ok], g[ok], gg[ok]
+            gg = np.where(gg > 1e-8, gg, np.inf)  # flat spots: leave in place, rejected below
             step = ((f - level) / gg)[:, None] * g
             step_n = np.linalg.norm(step, axis=1)
             # damp long steps so that candidates do not jump between sheets
             scale = np.minimum(1.0, 0.1 / np.maximum(step_n, 1e-300))[:, None]
-            P = P - scale * step
-            if np.all(np.abs(f - level) < 1e-13) and np.all(step_n < 1e-12):
-                break
-        f, g = _blob_f_grad(P, C, s2)
+            P[act] = Q - scale * step
+            done[act] = (np.abs(f - level) < 1e-14) | (step_n < 1e-15) | ~np.isfinite(gg)
+        f, _ = _blob_f_grad(P, C, s2)
         P = P[np.abs(f - level) < 1e-13]
         pts.append(P)
         have += len(P)
@@ -209,3 +212,24 @@ def surface_batch(count: int = 64, seed: int = 5, n_min: int = 2000, n_max: int 
             params = {"axes": ax.tolist()}
         out.append({"kind": kind, "X": X, "nrm": nrm, "n": n, "params": params})
     return out
+
+
+def cached(fn, *args, **kw):
+    """Call a generator, keeping its arrays in a .npz under $TMPDIR for reuse
+    by later processes on the same machine (plain arrays, no pickles)."""
+    import hashlib
+    import os
+    import tempfile
+
+    key = hashlib.sha1(repr((fn.__name__, args, sorted(kw.items()))).encode()).hexdigest()[:16]
+    d = os.path.join(os.environ.get("TMPDIR", tempfile.gettempdir()), "rbffd_synth_cache")
+    path = os.path.join(d, f"{fn.__name__}_{key}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return z["X"], z["nrm"]
+    X, nrm = fn(*args, **kw)
+    os.makedirs(d, exist_ok=True)
+    tmp = path + f".{os.getpid()}.tmp.npz"
+    np.savez(tmp, X=X, nrm=nrm)
+    os.replace(tmp, path)
+    return X, nrm

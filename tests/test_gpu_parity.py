@@ -1,0 +1,313 @@
+"""HIP path vs the CPU oracle, element by element on seeded inputs.
+
+Tolerances:
+  kNN            bit-exact (stencil lists in (d^2, index) order).
+  weights        per row: ||w_gpu - w_ora|| / ||w_ora|| <= max(1e-9, 0.5 kappa u),
+                 u = 2^-53, kappa = the oracle's kappa_2 of that stencil.  Two FP64
+                 codes of the same weights differ by the conditioning: against a
+                 60-digit truth the oracle sits at 0.01-0.06 kappa u (measured),
+                 so 0.5 kappa u bounds the sum of both errors.  Well-conditioned
+                 stencils (kappa <= 1.8e7) meet the literal 1e-9.
+  kappa_2        relative 20 kappa u + 1e-12: the smallest eigenvalue carries an
+                 absolute error of a few u ||A~|| in any backward-stable method.
+  eps (bisection) |eps_gpu - eps_ora| <= 2 eps_tol: a decision that differs where
+                 kappa(mid) ~ kappa_T lands both runs within tol of that mid.
+  SpMV FP64      1e-13 relative to sum_j |w_ij u_j| (row-wise).
+  RK4 FP64       1e-12 relative L2 of the trajectory end point.
+  RK4 FP32       1e-5 relative L2 against the FP64 oracle at the final time.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.knn import knn as oracle_knn
+from oracle.shape import bisect_eps, stencil_kappa
+from oracle.stepper import assemble, laplacian_apply, rk4
+from oracle.weights import build_weights as oracle_weights
+from synth import (blob, cached, fibonacci_sphere, jittered_torus, planar_patch, real_sph_harm,
+                   random_sph_harm_ic, schnakenberg_ic)
+
+pytestmark = pytest.mark.gpu
+U64 = 2.0 ** -53
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def weight_rule(wg, wo, kap):
+    err = np.linalg.norm(wg - wo, axis=1) / np.linalg.norm(wo, axis=1)
+    tol = np.maximum(1e-9, 0.5 * kap * U64)
+    return err, tol
+
+
+def oracle_kappas(X, idx, eps, rows, **kw):
+    eps = np.broadcast_to(np.asarray(eps, dtype=float), (len(idx),))
+    return np.array([stencil_kappa(X[idx[i]], eps[i], **kw) for i in rows])
+
+
+# ------------------------------------------------------------------ kNN ----
+
+@pytest.mark.parametrize("case", ["sphere2500_n31", "torus_n50", "blob_n50", "lattice_ties", "all_nodes"])
+def test_knn_exact(lib, case):
+    if case == "sphere2500_n31":
+        X, _ = fibonacci_sphere(2500); n = 31
+    elif case == "torus_n50":
+        X, _ = jittered_torus(40, 120); n = 50
+    elif case == "blob_n50":
+        X, _ = blob(3000, oversample=2.0); n = 50
+    elif case == "lattice_ties":
+        X, _ = planar_patch(23, spacing=0.125); n = 21      # many exact distance ties
+    else:
+        X, _ = fibonacci_sphere(37); n = 37                   # n = N
+    print(f"[knn] case={case} N={len(X)} n={n}", flush=True)
+    idx, perm = lib.knn(dev(X), n)
+    got = host(idx)
+    ref = oracle_knn(X, n)
+    assert np.array_equal(got, ref)
+    p = host(perm)
+    assert np.array_equal(np.sort(p), np.arange(len(X)))
+
+
+def test_knn_full_size_sampled(lib):
+    """N = 1e6 blob, n = 50 (the benchmark workload): sampled rows vs the oracle."""
+    X, _ = cached(blob, 1_000_000)
+    print("[knn] blob N=1e6 n=50", flush=True)
+    idx, _ = lib.knn(dev(X), 50)
+    got = host(idx)
+    rows = np.random.default_rng(7).choice(len(X), 300, replace=False)
+    ref = oracle_knn(X, 50, rows=rows)
+    assert np.array_equal(got[rows], ref)
+    assert np.all(got[:, 0] == np.arange(len(X)))
+
+
+# -------------------------------------------------------------- weights ----
+
+@pytest.fixture(scope="module")
+def sphere():
+    X, nrm = fibonacci_sphere(2500)
+    idx = oracle_knn(X, 31)
+    return X, nrm, idx
+
+
+@pytest.mark.parametrize("eps,literal", [(4.0, True), (2.0, False)])
+def test_weights_fixed_eps_sphere(lib, sphere, eps, literal):
+    X, nrm, idx = sphere
+    print(f"[weights] sphere N=2500 n=31 MQ deg2 eps={eps}", flush=True)
+    res = lib.build_weights(dev(X), dev(nrm), 31, idx=dev(idx, torch.int32), eps_mode="fixed", eps=eps)
+    wg = host(res.w)
+    rows = np.arange(0, 2500, 5)
+    wo = oracle_weights(X, nrm, idx, eps, rows=rows)
+    kap = oracle_kappas(X, idx, eps, rows)
+    err, tol = weight_rule(wg[rows], wo, kap)
+    if literal:
+        assert kap.max() < 1.8e7
+        assert err.max() <= 1e-9, err.max()
+    assert np.all(err <= tol), (err / tol).max()
+    assert np.all(host(res.status) == 0)
+    # kappa_2 parity
+    kg = host(res.kappa)[rows]
+    assert np.all(np.abs(kg / kap - 1.0) <= 20 * kap * U64 + 1e-12), np.abs(kg / kap - 1).max()
+
+
+@pytest.mark.parametrize("kernel,degree", [("imq", 0), ("mq", 1), ("ga", 2)])
+def test_weights_kernels_and_borders(lib, sphere, kernel, degree):
+    X, nrm, idx = sphere
+    eps = {"imq": 3.0, "mq": 3.0, "ga": 4.0}[kernel]
+    print(f"[weights] kernel={kernel} degree={degree} eps={eps}", flush=True)
+    res = lib.build_weights(dev(X), dev(nrm), 31, idx=dev(idx, torch.int32), eps_mode="fixed", eps=eps,
+                            kernel=kernel, degree=degree)
+    wg = host(res.w)
+    rows = np.arange(3, 2500, 17)
+    wo = oracle_weights(X, nrm, idx, eps, kernel=kernel, degree=degree, rows=rows)
+    kap = oracle_kappas(X, idx, eps, rows, kernel=kernel, degree=degree)
+    err, tol = weight_rule(wg[rows], wo, kap)
+    assert np.all(err <= tol), (err / tol).max()
+
+
+def test_weights_torus_given_eps_and_ragged(lib):
+    """Ragged N (not a multiple of anything), n = 50, per-stencil eps."""
+    X, nrm = jittered_torus(37, 111)  # N = 4107
+    n = 50
+    idx = oracle_knn(X, n)
+    rng = np.random.default_rng(11)
+    rho = np.sqrt(np.max(np.sum((X[idx] - X[idx[:, :1]]) ** 2, axis=2), axis=1))
+    eps = rng.uniform(0.6, 1.0, size=len(X)) / rho
+    print(f"[weights] torus N={len(X)} n=50 given eps", flush=True)
+    res = lib.build_weights(dev(X), dev(nrm), n, idx=dev(idx, torch.int32), eps_in=dev(eps), eps_mode="given")
+    wg = host(res.w)
+    rows = np.arange(0, len(X), 13)
+    wo = oracle_weights(X, nrm, idx, eps, rows=rows)
+    kap = oracle_kappas(X, idx, eps, rows)
+    err, tol = weight_rule(wg[rows], wo, kap)
+    assert np.all(err <= tol), (err / tol).max()
+    assert np.allclose(host(res.eps), eps, rtol=0, atol=0)
+
+
+def test_bisection_parity_torus(lib):
+    X, nrm = jittered_torus(40, 120)
+    n = 50
+    idx = oracle_knn(X, n)
+    print(f"[bisect] torus N={len(X)} n=50 kappa_T=1e12", flush=True)
+    res = lib.build_weights(dev(X), dev(nrm), n, idx=dev(idx, torch.int32), eps_mode="bisect", kappa_target=1e12)
+    eg, kg, st, ne = host(res.eps), host(res.kappa), host(res.status), host(res.nevals)
+    rows = np.random.default_rng(3).choice(len(X), 120, replace=False)
+    for i in rows:
+        eo, ko, evo, sto = bisect_eps(X[idx[i]], 1e12)
+        assert st[i] == sto == 0
+        assert abs(eg[i] - eo) <= 2e-4, (i, eg[i], eo)
+        assert abs(ne[i] - evo) <= 2
+    assert np.all(np.abs(np.log(kg / 1e12)) < 0.05)
+    # weights at the GPU's eps vs the oracle at that eps
+    wg = host(res.w)
+    sub = rows[:40]
+    wo = oracle_weights(X, nrm, idx, eg, rows=sub)
+    kap = oracle_kappas(X, idx, eg, sub)
+    err, tol = weight_rule(wg[sub], wo, kap)
+    assert np.all(err <= tol), (err / tol).max()
+
+
+def test_weights_without_given_stencils_runs_knn(lib, sphere):
+    X, nrm, idx = sphere
+    res = lib.build_weights(dev(X), dev(nrm), 31, eps_mode="fixed", eps=4.0)
+    assert np.array_equal(host(res.idx), idx)
+
+
+def test_duplicate_node_flagged(lib):
+    X, nrm = fibonacci_sphere(500)
+    X = X.copy()
+    X[10] = X[11]
+    res = lib.build_weights(dev(X), dev(nrm), 20, eps_mode="fixed", eps=3.0)
+    st = host(res.status)
+    assert st[10] == lib.ST_DUPLICATE and st[11] == lib.ST_DUPLICATE
+
+
+def test_argument_errors(lib):
+    X, nrm = fibonacci_sphere(40)
+    with pytest.raises(lib.RbffdError):
+        lib.build_weights(dev(X), dev(nrm), 41)          # n > N
+    with pytest.raises(lib.RbffdError):
+        lib.build_weights(dev(X), dev(nrm), 31, degree=3)
+    X2, nrm2 = fibonacci_sphere(200)
+    with pytest.raises(lib.RbffdError):
+        lib.build_weights(dev(X2), dev(nrm2), 60)        # n + border > 64 on this path
+    with pytest.raises(lib.RbffdError):
+        lib.build_weights(dev(X2), dev(nrm2), 31, eps_mode="given")   # eps_in missing
+    Xe = np.zeros((0, 3))
+    r = lib.build_weights(dev(Xe), dev(Xe), 31)          # empty input: nothing to do
+    assert r.w.shape == (0, 31)
+
+
+# -------------------------------------------------------- operator/step ----
+
+@pytest.fixture(scope="module")
+def sphere_op(lib, sphere):
+    X, nrm, idx = sphere
+    W = oracle_weights(X, nrm, idx, 2.0)
+    idx_d = dev(idx, torch.int32)
+    _, perm = lib.knn(dev(X), 31)
+    op = lib.Operator(idx_d, dev(W), perm=perm)
+    return X, idx, W, op
+
+
+def test_spmv_f64(lib, sphere_op):
+    X, idx, W, op = sphere_op
+    u = np.random.default_rng(1).standard_normal(len(X))
+    got = host(op.apply(dev(u), "f64"))
+    ref = laplacian_apply(idx, W, u)
+    scale = np.sum(np.abs(W * u[idx]), axis=1)
+    assert np.all(np.abs(got - ref) <= 1e-13 * scale)
+
+
+def test_spmv_f32_difference_form(lib, sphere_op):
+    X, idx, W, op = sphere_op
+    u = real_sph_harm(3, 1, X)
+    got = host(op.apply(dev(u), "f32"))
+    ref = laplacian_apply(idx, W, u)
+    scale = np.sum(np.abs(W), axis=1) * np.abs(u).max()
+    assert np.all(np.abs(got - ref) <= 2e-6 * scale)
+    # L 1 = 0 exactly in the difference form
+    one = host(op.apply(dev(np.ones(len(X))), "f32"))
+    assert np.all(one == 0.0)
+
+
+def test_rk4_f64_heat_sphere(lib, sphere_op):
+    """The unit-sphere heat workload: u0 = Y_6^3 + 0.1 Y_2^1, dt = 1e-4, 1000 steps."""
+    X, idx, W, op = sphere_op
+    u0 = real_sph_harm(6, 3, X) + 0.1 * real_sph_harm(2, 1, X)
+    print("[rk4] f64 heat sphere 1000 steps", flush=True)
+    got = host(op.step(dev(u0), 1e-4, 1000, prec="f64", graph_steps=50))[0]
+    (ref,) = rk4(assemble(idx, W), [u0], [1.0], dt=1e-4, nsteps=1000)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12
+    ue = math.exp(-4.2) * real_sph_harm(6, 3, X) + 0.1 * math.exp(-0.6) * real_sph_harm(2, 1, X)
+    assert np.linalg.norm(got - ue) / np.linalg.norm(ue) < 3e-3
+
+
+def test_rk4_f32_vs_f64_oracle(lib):
+    """FP32 state (difference form) against the FP64 oracle at t_final, N = 1e4."""
+    X, nrm = fibonacci_sphere(10000)
+    idx = oracle_knn(X, 31)
+    W = oracle_weights(X, nrm, idx, 4.0)
+    u0, _ = random_sph_harm_ic(X)
+    u0 = u0.astype(np.float32).astype(np.float64)
+    print("[rk4] f32 sphere N=1e4 200 steps", flush=True)
+    op = lib.Operator(dev(idx, torch.int32), dev(W))
+    dt = 2e-5
+    got = host(op.step(dev(u0), dt, 200, prec="f32", graph_steps=40))[0]
+    (ref,) = rk4(assemble(idx, W), [u0], [1.0], dt=dt, nsteps=200)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+
+
+def test_schnakenberg_two_species_f64_and_f32(lib, sphere_op):
+    X, idx, W, op = sphere_op
+    u0, v0 = schnakenberg_ic(len(X))
+    u0 = u0.astype(np.float32).astype(np.float64)
+    v0 = v0.astype(np.float32).astype(np.float64)
+    prm = {"a": 0.1, "b": 0.9, "gamma": 50.0}
+    D = [1.0, 10.0]
+    dt, steps = 5e-6, 100
+    (ru, rv) = rk4(assemble(idx, W), [u0, v0], D, "schnakenberg", prm, dt=dt, nsteps=steps)
+    st = dev(np.stack([u0, v0]))
+    g64 = host(op.step(st, dt, steps, prec="f64", D=D, reaction="schnakenberg", params=(0.1, 0.9, 50.0)))
+    assert np.linalg.norm(g64[0] - ru) / np.linalg.norm(ru) <= 1e-12
+    assert np.linalg.norm(g64[1] - rv) / np.linalg.norm(rv) <= 1e-12
+    g32 = host(op.step(st, dt, steps, prec="f32", D=D, reaction="schnakenberg", params=(0.1, 0.9, 50.0)))
+    assert np.linalg.norm(g32[0] - ru) / np.linalg.norm(ru) <= 1e-5
+    assert np.linalg.norm(g32[1] - rv) / np.linalg.norm(rv) <= 1e-5
+
+
+def test_graph_replay_matches_eager(lib, sphere_op):
+    X, idx, W, op = sphere_op
+    u0 = real_sph_harm(4, 2, X)
+    a = host(op.step(dev(u0), 1e-4, 120, prec="f64", graph_steps=1000))   # 120 < 1000: all eager
+    b = host(op.step(dev(u0), 1e-4, 120, prec="f64", graph_steps=30))     # 4 graph replays
+    c = host(op.step(dev(u0), 1e-4, 120, prec="f64", graph_steps=30))     # cached graph
+    assert np.array_equal(a, b) and np.array_equal(b, c)
+
+
+@pytest.mark.slow
+def test_weights_against_60_digit_truth(lib, sphere):
+    """GPU and oracle against 60-digit weights of the same stencils (kappa ~ 1e10):
+    the GPU error stays within max(2x the oracle's error, 0.1 kappa u)."""
+    from oracle.truth import stencil_weights_mp
+
+    X, nrm, idx = sphere
+    eps = 2.0
+    res = lib.build_weights(dev(X), dev(nrm), 31, idx=dev(idx, torch.int32), eps_mode="fixed", eps=eps)
+    wg = host(res.w)
+    for i in (0, 70, 1325, 1680, 2030, 2499):
+        s = idx[i]
+        wt = stencil_weights_mp(X[s], nrm[s], eps)
+        wo = oracle_weights(X, nrm, idx, eps, rows=[i])[0]
+        k = stencil_kappa(X[s], eps)
+        nt = np.linalg.norm(wt)
+        eg = np.linalg.norm(wg[i] - wt) / nt
+        eo = np.linalg.norm(wo - wt) / nt
+        assert eg <= max(2 * eo, 0.1 * k * U64) + 1e-12, (i, eg / (k * U64), eo / (k * U64))
