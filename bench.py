@@ -1,0 +1,243 @@
+"""Benchmark of the RBF-FD hot path on one MI355X.
+
+One step = one pass of the whole hot path over the point-cloud workload
+(implicit blob surface, N = 1e6 nodes, n = 50, Schnakenberg kinetics):
+  stencils (grid-hash kNN) -> per-stencil shape parameter -> FP64 weights ->
+  sparse operator -> `--rk4-steps` FP32 RK4 steps (default 10000).
+`value` is stencil weights per second (N / time of stencils + eps + weights);
+`ms_per_rk4_step` is the time of one RK4 step.  The shape parameter comes from
+the learned model with bisection fallback when a trained model is available
+(`--eps learned`), else from bisection (`--eps bisect`).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--rk4-steps R]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, TFLOP/s
+SCHNAK = (0.1, 0.9, 50.0)   # a, b, gamma
+DIFF = (1.0, 10.0)          # D_u, D_v
+
+
+def weights_flops(n, r, evals):
+    """Algorithmic FP64 flops of one stencil: per kappa_2 evaluation the
+    assembly (10 n^2) and Householder tridiagonalisation (4/3 m^3); then the
+    solves for the weights (30 m^2 + 40 n^2)."""
+    m = n + r
+    return evals * (4.0 / 3.0 * m ** 3 + 10.0 * n * n) + 30.0 * m * m + 40.0 * n * n
+
+
+def rk4_bytes_per_step(N, n, species=2, fp=4, ip=4):
+    """Algorithmic HBM bytes of one FP32 RK4 step (4 stage kernels): each stage
+    streams the (n-1) off-diagonal indices and weights of every row, and per
+    row reads/writes the species values: stage inputs 24/40/40/32 B for two
+    FP32 species (gathered input once, own state, accumulator, next input)."""
+    mat = 4 * N * (n - 1) * (fp + ip)
+    vec = N * species * fp * (3 + 5 + 5 + 4)
+    return mat + vec
+
+
+def spectral_radius(op, N, iters=300, seed=5):
+    import torch
+
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    v = torch.randn(N, dtype=torch.float64, device="cuda", generator=g)
+    lam = 0.0
+    for _ in range(iters):
+        v = op.apply(v, "f64")
+        lam = float(torch.linalg.vector_norm(v).item())
+        v = v / lam
+    return lam
+
+
+def cpu_baseline(X, nrm, idx, kappa_T, budget_s=15.0):
+    """Oracle (plain FP64 NumPy/LAPACK) weights with bisection on a bounded,
+    seeded sample of stencils, over a process pool of the host's cores.  Work
+    is handed out in small chunks; the clock stops when the time budget has
+    passed and the stencils finished by then are counted."""
+    from concurrent.futures import FIRST_COMPLETED, ProcessPoolExecutor, wait
+
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    rng = np.random.default_rng(12)
+    order = rng.permutation(len(idx))
+    chunk = 16
+    done = 0
+    t0 = time.perf_counter()
+    next_chunk = 0
+    with ProcessPoolExecutor(max_workers=cores) as ex:
+        pending = set()
+        while True:
+            while len(pending) < 2 * cores and time.perf_counter() - t0 < budget_s:
+                rows = idx[order[next_chunk * chunk:(next_chunk + 1) * chunk]]
+                next_chunk += 1
+                pending.add(ex.submit(_oracle_chunk, (X, nrm, rows, kappa_T)))
+            if not pending:
+                break
+            fin, pending = wait(pending, timeout=5.0, return_when=FIRST_COMPLETED)
+            done += sum(f.result() for f in fin)
+            print(f"[bench] cpu baseline: {done} stencils in {time.perf_counter() - t0:.1f} s", flush=True)
+            if time.perf_counter() - t0 >= budget_s:
+                # let the chunks already running finish, submit nothing new
+                for f in list(pending):
+                    done += f.result()
+                pending = set()
+                break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "stencil weights/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} seeded random stencils of the N={len(idx)} blob, bisection to kappa_T="
+                      f"{kappa_T:g} then weights (oracle route), {dt:.1f} s on {cores} processes"}
+
+
+def _oracle_chunk(args):
+    X, nrm, rows, kT = args
+    from oracle.shape import bisect_eps
+    from oracle.weights import stencil_weights
+
+    out = []
+    for s in rows:
+        eps, _, _, _ = bisect_eps(X[s], kT)
+        out.append(stencil_weights(X[s], nrm[s], eps))
+    return len(out)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=1_000_000)
+    ap.add_argument("--n", type=int, default=50)
+    ap.add_argument("--rk4-steps", type=int, default=10000)
+    ap.add_argument("--eps", choices=["bisect", "learned"], default="bisect")
+    ap.add_argument("--kappa", type=float, default=1e12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_1404_0812_amd as rb
+    from synth import blob, cached, schnakenberg_ic
+
+    t_gen = time.perf_counter()
+    X, nrm = cached(blob, args.N)
+    print(f"[bench] blob N={args.N} ready in {time.perf_counter() - t_gen:.1f} s", flush=True)
+    torch.cuda.set_device(0)
+    ctx = rb.Context(0)
+    Xd = torch.as_tensor(X).cuda()
+    Nd = torch.as_tensor(nrm).cuda()
+    u0, v0 = schnakenberg_ic(args.N)
+    state0 = torch.as_tensor(np.stack([u0, v0])).cuda()
+    n = args.n
+    st = ctx.stream
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(st)
+        return e
+
+    dt_rk4 = None
+    rho_hat = None
+    rows = []
+    total_steps = args.warmup + args.steps
+    torch.cuda.synchronize()
+    for it in range(total_steps):
+        timed = it >= args.warmup
+        torch.cuda.synchronize()
+        t_wall0 = time.perf_counter()
+        e0 = ev()
+        idx, perm = rb.knn(Xd, n, ctx=ctx)
+        e1 = ev()
+        res = rb.build_weights(Xd, Nd, n, idx=idx, ctx=ctx, eps_mode="bisect", kappa_target=args.kappa)
+        e2 = ev()
+        op = rb.Operator(idx, res.w, perm=perm, ctx=ctx)
+        e3 = ev()
+        if dt_rk4 is None:
+            # RK4 stability (real-axis interval 2.785): dt = 0.5 * 2.785 / (D_max rho(L)),
+            # rho(L) from 300 power iterations with the library's operator (setup,
+            # untimed); the top of the spectrum is clustered, so the margin is wide
+            rho_hat = spectral_radius(op, args.N)
+            dt_rk4 = 0.5 * 2.785 / (max(DIFF) * rho_hat)
+            e3 = ev()
+        out = op.step(state0, dt_rk4, args.rk4_steps, prec="f32", D=DIFF, reaction="schnakenberg",
+                      params=SCHNAK, graph_steps=100)
+        e4 = ev()
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter() - t_wall0
+        r = {"knn": e0.elapsed_time(e1), "weights": e1.elapsed_time(e2), "op": e2.elapsed_time(e3),
+             "rk4": e3.elapsed_time(e4), "wall": t_wall * 1e3}
+        print(f"[bench] pass {it} {'timed' if timed else 'warmup'}: " +
+              " ".join(f"{k}={v:.1f}ms" for k, v in r.items()), flush=True)
+        if timed:
+            rows.append(r)
+        if it == total_steps - 1:
+            nevals = res.nevals.cpu().numpy()
+            status = res.status.cpu().numpy()
+            kap = res.kappa.cpu().numpy()
+            fin = out.cpu().numpy()
+        del op
+
+    med = {k: float(np.median([r[k] for r in rows])) for k in rows[0]}
+    t_weights_s = (med["knn"] + med["weights"]) / 1e3
+    value = args.N / t_weights_s
+    ms_rk4 = med["rk4"] / args.rk4_steps
+    # roofline: the dominant kernel of the pass
+    r_border = 10
+    flops = float(np.sum(weights_flops(n, r_border, nevals.astype(np.float64))))
+    w_tflops = flops / (med["weights"] / 1e3) / 1e12
+    bytes_step = rk4_bytes_per_step(args.N, n)
+    rk4_gbs = bytes_step / (ms_rk4 / 1e3) / 1e9
+    roof_w = {"bound": "alu", "achieved": w_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+              "frac": w_tflops / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_weights (FP64 VALU)"}
+    roof_s = {"bound": "hbm", "achieved": rk4_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rk4_stage (ELL SpMV + RK4)"}
+    dominant_is_rk4 = med["rk4"] >= med["weights"]
+    line = {
+        "metric": "stencil weights/s + ms per RK4 step at N=1e6,n=50; learned-eps vs bisection",
+        "value": value,
+        "unit": "stencil weights/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sum(med[k] for k in ("knn", "weights", "op", "rk4")),
+        "ms_per_rk4_step": ms_rk4,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 weights / f32 state",
+        "data": "synthetic",
+        "config": {"workload": f"implicit blob point cloud N={args.N}, n={n}, MQ + degree-2 border, "
+                               f"eps by {args.eps} to kappa_T={args.kappa:g}, Schnakenberg FP32 RK4 "
+                               f"x{args.rk4_steps}", "N": args.N, "n": n, "rk4_steps": args.rk4_steps,
+                   "rk4_dt": dt_rk4, "rho_L": rho_hat, "eps_mode": args.eps},
+        "phases_ms": med,
+        "roofline": roof_s if dominant_is_rk4 else roof_w,
+        "roofline_other": roof_w if dominant_is_rk4 else roof_s,
+        "weights_stats": {"mean_kappa_evals": float(nevals.mean()), "status_counts":
+                          {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+                          "median_log10_kappa": float(np.median(np.log10(kap)))},
+        "state_finite": bool(np.isfinite(fin).all()),
+    }
+    if not args.no_cpu_baseline:
+        idx_h = idx.cpu().numpy()
+        line["cpu_baseline"] = cpu_baseline(X, nrm, idx_h, args.kappa, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -46,13 +46,15 @@ __global__ void k_build_ell(int64_t N, int n, const int32_t* __restrict__ idx, c
     }
 }
 
+// State lives species-interleaved in internal order: element (p, s) at p*S + s,
+// so that one gather fetches every species of a neighbour.
 template <typename T>
 __global__ void k_load_state(int64_t N, int S, const double* __restrict__ in, const int32_t* __restrict__ perm,
                              T* __restrict__ out) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= N) return;
     int64_t i = perm ? perm[p] : p;
-    for (int s = 0; s < S; ++s) out[s * N + p] = (T)in[s * N + i];
+    for (int s = 0; s < S; ++s) out[p * S + s] = (T)in[s * N + i];
 }
 
 template <typename T>
@@ -61,7 +63,7 @@ __global__ void k_store_state(int64_t N, int S, const T* __restrict__ in, const 
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= N) return;
     int64_t i = perm ? perm[p] : p;
-    for (int s = 0; s < S; ++s) out[s * N + i] = (double)in[s * N + p];
+    for (int s = 0; s < S; ++s) out[s * N + i] = (double)in[p * S + s];
 }
 
 struct ReactParams {
@@ -94,90 +96,141 @@ struct StageArgs {
     ReactParams rp;
 };
 
-// L applied to the stage input Y (S species), FP32 difference form
-template <int S>
-__device__ __forceinline__ void apply_rows_f32(const StageArgs& a, const int32_t* __restrict__ idx,
-                                               const float* __restrict__ w, const float* __restrict__ Y, int64_t p,
-                                               const float (&yi)[2], float (&acc)[2]) {
+// Blocks are dispatched round-robin over the 8 XCDs; remap them so that each
+// XCD works on one contiguous range of rows (its L2 then holds the part of the
+// gathered state those rows touch).
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t x = b & 7, q = nb >> 3, rem = nb & 7;
+    return x * q + (x < rem ? x : rem) + (b >> 3);
+}
+
+template <typename T, int S>
+struct Vec;
+template <>
+struct Vec<float, 1> { using type = float; };
+template <>
+struct Vec<float, 2> { using type = float2; };
+template <>
+struct Vec<double, 1> { using type = double; };
+template <>
+struct Vec<double, 2> { using type = double2; };
+
+template <typename T, int S>
+__device__ __forceinline__ void vload(const T* __restrict__ Y, int64_t j, T (&v)[2]) {
+    if constexpr (S == 2) {
+        const typename Vec<T, 2>::type t = reinterpret_cast<const typename Vec<T, 2>::type*>(Y)[j];
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+        v[0] = Y[j];
+        v[1] = (T)0;
+    }
+}
+template <typename T, int S>
+__device__ __forceinline__ void vstore(T* __restrict__ Y, int64_t j, const T (&v)[2]) {
+    if constexpr (S == 2) {
+        typename Vec<T, 2>::type t;
+        t.x = v[0];
+        t.y = v[1];
+        reinterpret_cast<typename Vec<T, 2>::type*>(Y)[j] = t;
+    } else {
+        Y[j] = v[0];
+    }
+}
+
+constexpr int CHUNK = 8;
+
+// L applied to the stage input of row p.  FP32: difference form over the n-1
+// off-diagonal slots; FP64: plain form over all n slots in slot order.
+template <typename T, int S>
+__device__ __forceinline__ void apply_row(const StageArgs& a, const int32_t* __restrict__ idx,
+                                          const T* __restrict__ w, const T* __restrict__ Y, int64_t p,
+                                          const T (&yi)[2], T (&acc)[2]) {
     const int64_t N = a.N;
-    float s0 = 0.f, s1 = 0.f, t0 = 0.f, t1 = 0.f;
-    int k = 0;
-    for (; k + 2 <= a.nslots; k += 2) {
-        const int j0 = __builtin_nontemporal_load(idx + (int64_t)k * N + p);
-        const int j1 = __builtin_nontemporal_load(idx + (int64_t)(k + 1) * N + p);
-        const float w0 = __builtin_nontemporal_load(w + (int64_t)k * N + p);
-        const float w1 = __builtin_nontemporal_load(w + (int64_t)(k + 1) * N + p);
-        s0 = fmaf(w0, Y[j0] - yi[0], s0);
-        s1 = fmaf(w1, Y[j1] - yi[0], s1);
-        if (S == 2) {
-            t0 = fmaf(w0, Y[N + j0] - yi[1], t0);
-            t1 = fmaf(w1, Y[N + j1] - yi[1], t1);
+    const int ns = a.nslots;
+    constexpr bool diff = sizeof(T) == 4;
+    T s0 = 0, s1 = 0;
+    int k0 = 0;
+    for (; k0 + CHUNK <= ns; k0 += CHUNK) {
+        int j[CHUNK];
+        T wk[CHUNK];
+#pragma unroll
+        for (int t = 0; t < CHUNK; ++t) {
+            j[t] = __builtin_nontemporal_load(idx + (int64_t)(k0 + t) * N + p);
+            wk[t] = __builtin_nontemporal_load(w + (int64_t)(k0 + t) * N + p);
+        }
+#pragma unroll
+        for (int t = 0; t < CHUNK; ++t) {
+            T y[2];
+            vload<T, S>(Y, j[t], y);
+            if (diff) {
+                s0 = fma(wk[t], y[0] - yi[0], s0);
+                if (S == 2) s1 = fma(wk[t], y[1] - yi[1], s1);
+            } else {
+                s0 = fma(wk[t], y[0], s0);
+                if (S == 2) s1 = fma(wk[t], y[1], s1);
+            }
         }
     }
-    if (k < a.nslots) {
-        const int j0 = __builtin_nontemporal_load(idx + (int64_t)k * N + p);
-        const float w0 = __builtin_nontemporal_load(w + (int64_t)k * N + p);
-        s0 = fmaf(w0, Y[j0] - yi[0], s0);
-        if (S == 2) t0 = fmaf(w0, Y[N + j0] - yi[1], t0);
-    }
-    acc[0] = s0 + s1;
-    acc[1] = t0 + t1;
-}
-
-// FP64 plain form over all n slots, in slot order
-template <int S>
-__device__ __forceinline__ void apply_rows_f64(const StageArgs& a, const int32_t* __restrict__ idx,
-                                               const double* __restrict__ w, const double* __restrict__ Y,
-                                               int64_t p, double (&acc)[2]) {
-    const int64_t N = a.N;
-    double s0 = 0.0, t0 = 0.0;
-    for (int k = 0; k < a.nslots; ++k) {
-        const int j = idx[(int64_t)k * N + p];
-        const double wk = w[(int64_t)k * N + p];
-        s0 = fma(wk, Y[j], s0);
-        if (S == 2) t0 = fma(wk, Y[N + j], t0);
+    for (int k = k0; k < ns; ++k) {
+        const int j = __builtin_nontemporal_load(idx + (int64_t)k * N + p);
+        const T wk = __builtin_nontemporal_load(w + (int64_t)k * N + p);
+        T y[2];
+        vload<T, S>(Y, j, y);
+        if (diff) {
+            s0 = fma(wk, y[0] - yi[0], s0);
+            if (S == 2) s1 = fma(wk, y[1] - yi[1], s1);
+        } else {
+            s0 = fma(wk, y[0], s0);
+            if (S == 2) s1 = fma(wk, y[1], s1);
+        }
     }
     acc[0] = s0;
-    acc[1] = t0;
+    acc[1] = s1;
 }
 
-// RK4 stage `st` (0..3).  Y: stage input; U: state at the start of the step;
+// RK4 stage `ST` (0..3).  Y: stage input; U: state at the start of the step;
 // ACC: accumulator; YN: next stage input (stages 0-2) -- stage 3 updates U.
 template <typename T, int S, int R, int ST>
 __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* __restrict__ idx,
                                                    const T* __restrict__ w, const T* __restrict__ Y,
                                                    T* __restrict__ U, T* __restrict__ ACC, T* __restrict__ YN) {
-    const int64_t p = blockIdx.x * (int64_t)BLK + threadIdx.x;
-    const int64_t N = a.N;
-    if (p >= N) return;
-    T yi[2] = {Y[p], S == 2 ? Y[N + p] : (T)0};
+    const int64_t p = xcd_block() * BLK + threadIdx.x;
+    if (p >= a.N) return;
+    T yi[2];
+    vload<T, S>(Y, p, yi);
     T lap[2];
-    if constexpr (sizeof(T) == 4) {
-        apply_rows_f32<S>(a, idx, (const float*)w, (const float*)Y, p, yi, lap);
-    } else {
-        apply_rows_f64<S>(a, idx, (const double*)w, (const double*)Y, p, lap);
-    }
+    apply_row<T, S>(a, idx, w, Y, p, yi, lap);
     T r[2];
     reaction<T, R>(yi, r, a.rp);
     T k[2];
     k[0] = (T)a.D[0] * lap[0] + r[0];
     k[1] = (T)a.D[1] * lap[1] + r[1];
     const T dt = (T)a.dt;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int64_t q = s * N + p;
-        if (ST == 0) {
-            ACC[q] = k[s];
-            YN[q] = U[q] + (T)0.5 * dt * k[s];
-        } else if (ST == 1) {
-            ACC[q] = ACC[q] + (T)2 * k[s];
-            YN[q] = U[q] + (T)0.5 * dt * k[s];
-        } else if (ST == 2) {
-            ACC[q] = ACC[q] + (T)2 * k[s];
-            YN[q] = U[q] + dt * k[s];
-        } else {
-            U[q] = U[q] + dt / (T)6 * (ACC[q] + k[s]);
-        }
+    T u[2], c[2], o[2];
+    if (ST == 0) {
+        vload<T, S>(U, p, u);
+        o[0] = u[0] + (T)0.5 * dt * k[0];
+        o[1] = u[1] + (T)0.5 * dt * k[1];
+        vstore<T, S>(ACC, p, k);
+        vstore<T, S>(YN, p, o);
+    } else if (ST == 1 || ST == 2) {
+        vload<T, S>(U, p, u);
+        vload<T, S>(ACC, p, c);
+        const T h = ST == 1 ? (T)0.5 * dt : dt;
+        o[0] = u[0] + h * k[0];
+        o[1] = u[1] + h * k[1];
+        c[0] = c[0] + (T)2 * k[0];
+        c[1] = c[1] + (T)2 * k[1];
+        vstore<T, S>(ACC, p, c);
+        vstore<T, S>(YN, p, o);
+    } else {
+        vload<T, S>(U, p, u);
+        vload<T, S>(ACC, p, c);
+        o[0] = u[0] + dt / (T)6 * (c[0] + k[0]);
+        o[1] = u[1] + dt / (T)6 * (c[1] + k[1]);
+        vstore<T, S>(U, p, o);
     }
 }
 
@@ -185,15 +238,12 @@ __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* _
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_apply(StageArgs a, const int32_t* __restrict__ idx, const T* __restrict__ w,
                                                const T* __restrict__ Y, T* __restrict__ out) {
-    const int64_t p = blockIdx.x * (int64_t)BLK + threadIdx.x;
+    const int64_t p = xcd_block() * BLK + threadIdx.x;
     if (p >= a.N) return;
-    T yi[2] = {Y[p], (T)0};
+    T yi[2];
+    vload<T, 1>(Y, p, yi);
     T lap[2];
-    if constexpr (sizeof(T) == 4) {
-        apply_rows_f32<1>(a, idx, (const float*)w, (const float*)Y, p, yi, lap);
-    } else {
-        apply_rows_f64<1>(a, idx, (const double*)w, (const double*)Y, p, lap);
-    }
+    apply_row<T, 1>(a, idx, w, Y, p, yi, lap);
     out[p] = lap[0];
 }
 

@@ -16,6 +16,8 @@ import math
 
 import numpy as np
 
+GENERATOR_VERSION = 2  # part of the cache key; bump when a generator changes
+
 __all__ = [
     "fibonacci_sphere",
     "jittered_torus",
@@ -99,9 +101,9 @@ def blob(N: int, seed: int = 4, ncentres: int = 8, s2: float = 0.3, level: float
 
     Centres are U([-1,1]^3) (seeded).  Candidates drawn uniformly in a box
     around the centres are kept near the level set, Newton-projected onto it
-    until |f - level| < 1e-13, and thinned on a uniform grid (at most one node
-    per cell, in a seeded random order) to exactly N nodes.  Normals are
-    -grad f / |grad f| (outward, since f decreases outwards).
+    until |f - level| < 1e-13, and thinned to a Poisson-disk set (no two nodes
+    closer than half the grid spacing, see _poisson_disk) of exactly N nodes.
+    Normals are -grad f / |grad f| (outward, since f decreases outwards).
     """
     rng = np.random.default_rng(seed)
     C = rng.uniform(-1.0, 1.0, size=(ncentres, 3))
@@ -135,37 +137,70 @@ def blob(N: int, seed: int = 4, ncentres: int = 8, s2: float = 0.3, level: float
         pts.append(P)
         have += len(P)
     P = np.concatenate(pts)[:need]
-    # area-scale estimate from the candidate count is not needed: thin with a
-    # cell size found by bisection so that at least N cells are occupied.
-    perm = rng.permutation(len(P))
-    P = P[perm]
-    ext = hi - lo
-
-    def occupied(h):
-        key = np.floor((P - lo) / h).astype(np.int64)
-        dims = np.floor(ext / h).astype(np.int64) + 2
-        lin = (key[:, 0] * dims[1] + key[:, 1]) * dims[2] + key[:, 2]
-        _, first = np.unique(lin, return_index=True)
-        return np.sort(first)
-
-    h_lo, h_hi = 1e-6, float(ext.max())
-    keep = None
-    for _ in range(60):
-        h = math.sqrt(h_lo * h_hi)
-        k = occupied(h)
-        if len(k) >= N:
-            h_lo, keep = h, k
-        else:
-            h_hi = h
-        if h_hi / h_lo < 1.0 + 1e-4:
-            break
-    if keep is None:
-        raise RuntimeError("blob: not enough candidates")
-    keep = keep[np.sort(rng.permutation(len(keep))[:N])]
-    X = P[keep]
+    P = P[rng.permutation(len(P))]
+    X = _poisson_disk(P, N, lo, hi, rng)
     _, g = _blob_f_grad(X, C, s2)
     nrm = -g / np.linalg.norm(g, axis=1, keepdims=True)
     return np.ascontiguousarray(X), np.ascontiguousarray(nrm)
+
+
+def _grid_first(P, lo, ext, h):
+    key = np.floor((P - lo) / h).astype(np.int64)
+    dims = np.floor(ext / h).astype(np.int64) + 2
+    lin = (key[:, 0] * dims[1] + key[:, 1]) * dims[2] + key[:, 2]
+    _, first = np.unique(lin, return_index=True)
+    return np.sort(first)
+
+
+def _mis(Q, r, prio):
+    """Maximal independent set of the graph 'closer than r' (parallel rounds:
+    a node joins when its priority beats every undecided neighbour's)."""
+    from scipy.spatial import cKDTree
+
+    pairs = cKDTree(Q).query_pairs(r, output_type="ndarray")
+    keep = np.zeros(len(Q), dtype=bool)
+    und = np.ones(len(Q), dtype=bool)
+    i, j = pairs[:, 0], pairs[:, 1]
+    while und.any():
+        act = und[i] & und[j]
+        mx = np.full(len(Q), -1.0)
+        np.maximum.at(mx, i[act], prio[j[act]])
+        np.maximum.at(mx, j[act], prio[i[act]])
+        win = und & (prio > mx)
+        keep |= win
+        und &= ~win
+        lose = np.zeros(len(Q), dtype=bool)
+        lose[j[win[i] & und[j]]] = True
+        lose[i[win[j] & und[i]]] = True
+        und &= ~lose
+    return np.flatnonzero(keep)
+
+
+def _poisson_disk(P, N, lo, hi, rng):
+    """Exactly N of the candidates P with no two closer than h/2, where h is a
+    grid spacing: keep the first candidate of each grid cell, drop close pairs
+    by a maximal independent set, shrink h until at least N remain, then keep
+    a seeded random N of them."""
+    ext = hi - lo
+    h_lo, h_hi = 1e-6, float(ext.max())
+    for _ in range(60):  # largest h whose grid holds ~1.4 N candidates
+        h = math.sqrt(h_lo * h_hi)
+        if len(_grid_first(P, lo, ext, h)) >= 1.4 * N:
+            h_lo = h
+        else:
+            h_hi = h
+        if h_hi / h_lo < 1.0 + 1e-3:
+            break
+    h = h_lo
+    for _ in range(20):
+        k = _grid_first(P, lo, ext, h)
+        Q = P[k]
+        keep = _mis(Q, 0.5 * h, rng.random(len(Q)))
+        if len(keep) >= N:
+            sel = np.sort(rng.permutation(len(keep))[:N])
+            return Q[keep[sel]]
+        h *= 0.95
+    raise RuntimeError("blob: not enough candidates for the Poisson-disk set")
 
 
 def planar_patch(n_side: int, spacing: float = 0.125, seed: int | None = None, jitter: float = 0.0):
@@ -221,7 +256,7 @@ def cached(fn, *args, **kw):
     import os
     import tempfile
 
-    key = hashlib.sha1(repr((fn.__name__, args, sorted(kw.items()))).encode()).hexdigest()[:16]
+    key = hashlib.sha1(repr((GENERATOR_VERSION, fn.__name__, args, sorted(kw.items()))).encode()).hexdigest()[:16]
     d = os.path.join(os.environ.get("TMPDIR", tempfile.gettempdir()), "rbffd_synth_cache")
     path = os.path.join(d, f"{fn.__name__}_{key}.npz")
     if os.path.exists(path):
