@@ -112,6 +112,22 @@ def _oracle_chunk(args):
     return len(out)
 
 
+def training_sets(scale=1.0):
+    """Seeded node sets for the labels (none of them is the benchmark blob):
+    two Poisson-disk blobs with other centres, jittered tori and ellipsoids."""
+    from synth import blob, cached, ellipsoid, jittered_torus, torus_grid_for_count
+
+    rng = np.random.default_rng(31)
+    out = [cached(blob, int(500_000 * scale), seed=14), cached(blob, int(500_000 * scale), seed=24)]
+    for k in range(4):
+        R = float(rng.uniform(0.6, 1.8))
+        r = R * float(rng.uniform(0.22, 0.42))
+        out.append(jittered_torus(*torus_grid_for_count(int(150_000 * scale), R, r), R, r, seed=200 + k))
+    for k in range(4):
+        out.append(ellipsoid(int(100_000 * scale), *rng.uniform(0.5, 2.0, size=3)))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,8 +136,12 @@ def main():
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--rk4-steps", type=int, default=10000)
-    ap.add_argument("--eps", choices=["bisect", "learned"], default="bisect")
-    ap.add_argument("--kappa", type=float, default=1e12)
+    ap.add_argument("--eps", choices=["bisect", "learned"], default="learned")
+    ap.add_argument("--kappa", type=float, default=1e10)
+    ap.add_argument("--literal-kappa", type=float, default=1e12)
+    ap.add_argument("--train-scale", type=float, default=1.0)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args()
@@ -132,6 +152,7 @@ def main():
     import torch
 
     import paper_1404_0812_amd as rb
+    from paper_1404_0812_amd import learned
     from synth import blob, cached, schnakenberg_ic
 
     t_gen = time.perf_counter()
@@ -145,11 +166,36 @@ def main():
     state0 = torch.as_tensor(np.stack([u0, v0])).cuda()
     n = args.n
     st = ctx.stream
+    band = (args.kappa / 10.0, args.kappa * 10.0)
 
     def ev():
         e = torch.cuda.Event(enable_timing=True)
         e.record(st)
         return e
+
+    tsets = training_sets(args.train_scale) if args.eps == "learned" else None
+
+    def make_net(kT):
+        t0 = time.perf_counter()
+        feats, labels = [], []
+        for Xt, nt in tsets:
+            f, y = learned.label_node_set(Xt, nt, n, kT, ctx=ctx)
+            feats.append(f)
+            labels.append(y)
+        feats = torch.cat(feats)
+        labels = torch.cat(labels)
+        t_lab = time.perf_counter() - t0
+        print(f"[bench] {feats.shape[0]} bisection labels (kappa_T={kT:g}) in {t_lab:.1f} s", flush=True)
+        nt_, losses, t_train = learned.train(feats, labels, epochs=args.epochs, ctx=ctx)
+        info = {"kappa_target": kT, "samples": int(feats.shape[0]), "label_s": t_lab, "train_s": t_train,
+                "steps": int(losses.numel()), "final_batch_mse": float(losses[-100:].mean().item()),
+                "label_mean": float(labels.mean().item()), "label_std": float(labels.std().item())}
+        return nt_, info, float(torch.exp(labels.mean()).item())
+
+    train_info = None
+    net = None
+    if args.eps == "learned":
+        net, train_info, c_const = make_net(args.kappa)
 
     dt_rk4 = None
     rho_hat = None
@@ -163,7 +209,14 @@ def main():
         e0 = ev()
         idx, perm = rb.knn(Xd, n, ctx=ctx)
         e1 = ev()
-        res = rb.build_weights(Xd, Nd, n, idx=idx, ctx=ctx, eps_mode="bisect", kappa_target=args.kappa)
+        if net is not None:
+            eps_hat = net.predict_eps(Xd, Nd, idx)
+            e1b = ev()
+            res = rb.build_weights(Xd, Nd, n, idx=idx, eps_in=eps_hat, ctx=ctx, eps_mode="learned",
+                                   kappa_target=args.kappa, band=band)
+        else:
+            e1b = e1
+            res = rb.build_weights(Xd, Nd, n, idx=idx, ctx=ctx, eps_mode="bisect", kappa_target=args.kappa)
         e2 = ev()
         op = rb.Operator(idx, res.w, perm=perm, ctx=ctx)
         e3 = ev()
@@ -179,8 +232,8 @@ def main():
         e4 = ev()
         torch.cuda.synchronize()
         t_wall = time.perf_counter() - t_wall0
-        r = {"knn": e0.elapsed_time(e1), "weights": e1.elapsed_time(e2), "op": e2.elapsed_time(e3),
-             "rk4": e3.elapsed_time(e4), "wall": t_wall * 1e3}
+        r = {"knn": e0.elapsed_time(e1), "predict": e1.elapsed_time(e1b), "weights": e1b.elapsed_time(e2),
+             "op": e2.elapsed_time(e3), "rk4": e3.elapsed_time(e4), "wall": t_wall * 1e3}
         print(f"[bench] pass {it} {'timed' if timed else 'warmup'}: " +
               " ".join(f"{k}={v:.1f}ms" for k, v in r.items()), flush=True)
         if timed:
@@ -193,10 +246,9 @@ def main():
         del op
 
     med = {k: float(np.median([r[k] for r in rows])) for k in rows[0]}
-    t_weights_s = (med["knn"] + med["weights"]) / 1e3
+    t_weights_s = (med["knn"] + med["predict"] + med["weights"]) / 1e3
     value = args.N / t_weights_s
     ms_rk4 = med["rk4"] / args.rk4_steps
-    # roofline: the dominant kernel of the pass
     r_border = 10
     flops = float(np.sum(weights_flops(n, r_border, nevals.astype(np.float64))))
     w_tflops = flops / (med["weights"] / 1e3) / 1e12
@@ -207,6 +259,72 @@ def main():
     roof_s = {"bound": "hbm", "achieved": rk4_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rk4_stage (ELL SpMV + RK4)"}
     dominant_is_rk4 = med["rk4"] >= med["weights"]
+
+    def growth_rate(w_tensor, idx_t, perm_t):
+        """Largest growth rate of du/dt = L u seen by FP64 RK4 from a random start
+        (negative: every mode decays; positive: an eigenvalue with Re > 0)."""
+        op_ = rb.Operator(idx_t, w_tensor, perm=perm_t, ctx=ctx)
+        rho_m = float(w_tensor.abs().sum(1).median().item())
+        dt_ = 0.2 / rho_m
+        v = torch.as_tensor(np.random.default_rng(0).standard_normal(args.N)).cuda()
+        prev, rate = None, float("nan")
+        for _ in range(8):
+            v = op_.step(v, dt_, 100, prec="f64", graph_steps=100)[0]
+            nv = float(torch.linalg.vector_norm(v).item())
+            if prev is not None:
+                rate = math.log(nv / prev) / (100 * dt_)
+            prev = nv
+            if not math.isfinite(nv) or nv > 1e30:
+                break
+        del op_
+        return rate
+
+    def compare_methods(net_, kT, band_, c_const_):
+        idx_c, perm_c = rb.knn(Xd, n, ctx=ctx)
+        out_c = {"kappa_target": kT, "band": list(band_)}
+
+        def timed_weights(**kw):
+            torch.cuda.synchronize()
+            a = ev()
+            rr = rb.build_weights(Xd, Nd, n, idx=idx_c, ctx=ctx, kappa_target=kT, band=band_, **kw)
+            b = ev()
+            torch.cuda.synchronize()
+            k = rr.kappa.cpu().numpy()
+            return rr, {"ms": a.elapsed_time(b), "mean_kappa_evals": float(rr.nevals.float().mean().item()),
+                        "fallback_rate": float((rr.status == 1).float().mean().item()),
+                        "in_band": float(np.mean((k > 0.99 * band_[0]) & (k < 1.01 * band_[1]))),
+                        "log10_kappa_p1_p50_p99": [float(v) for v in np.percentile(np.log10(k), [1, 50, 99])]}
+
+        rr, out_c["bisect"] = timed_weights(eps_mode="bisect")
+        out_c["operator_growth_rate"] = growth_rate(rr.w, idx_c, perm_c)
+        print(f"[bench] compare kappa_T={kT:g}: bisect {out_c['bisect']['ms']:.1f} ms, growth rate "
+              f"{out_c['operator_growth_rate']:.3e}", flush=True)
+        _, out_c["bisect_band_stop"] = timed_weights(eps_mode="bisect", band_stop=True)
+        if net_ is not None:
+            a = ev()
+            eps_hat = net_.predict_eps(Xd, Nd, idx_c)
+            b = ev()
+            torch.cuda.synchronize()
+            _, out_c["learned"] = timed_weights(eps_mode="learned", eps_in=eps_hat)
+            out_c["learned"]["predict_ms"] = a.elapsed_time(b)
+            eps_c = learned.constant_eps(Xd, Nd, idx_c, c_const_, ctx=ctx)
+            _, out_c["constant_eps_rho"] = timed_weights(eps_mode="learned", eps_in=eps_c)
+            out_c["constant_eps_rho"]["c"] = c_const_
+            L = out_c["learned"]["ms"] + out_c["learned"]["predict_ms"]
+            out_c["speedup_learned_vs_bisect"] = out_c["bisect"]["ms"] / L
+            out_c["speedup_learned_vs_band_stop"] = out_c["bisect_band_stop"]["ms"] / L
+            out_c["speedup_learned_vs_constant"] = out_c["constant_eps_rho"]["ms"] / L
+        return out_c
+
+    compare = None
+    if not args.no_compare:
+        compare = compare_methods(net, args.kappa, band, c_const if net is not None else None)
+        if args.literal_kappa and args.literal_kappa != args.kappa:
+            net_l, info_l, c_l = make_net(args.literal_kappa) if net is not None else (None, None, None)
+            lit = compare_methods(net_l, args.literal_kappa, (args.literal_kappa / 10, args.literal_kappa * 10), c_l)
+            lit["training"] = info_l
+            compare = {"run_target": compare, "literal_target": lit}
+
     line = {
         "metric": "stencil weights/s + ms per RK4 step at N=1e6,n=50; learned-eps vs bisection",
         "value": value,
@@ -214,17 +332,17 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": sum(med[k] for k in ("knn", "weights", "op", "rk4")),
+        "ms_per_step": sum(med[k] for k in ("knn", "predict", "weights", "op", "rk4")),
         "ms_per_rk4_step": ms_rk4,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 weights / f32 state",
+        "dtype": "f64 weights / f32 state / bf16 mlp",
         "data": "synthetic",
         "config": {"workload": f"implicit blob point cloud N={args.N}, n={n}, MQ + degree-2 border, "
-                               f"eps by {args.eps} to kappa_T={args.kappa:g}, Schnakenberg FP32 RK4 "
-                               f"x{args.rk4_steps}", "N": args.N, "n": n, "rk4_steps": args.rk4_steps,
-                   "rk4_dt": dt_rk4, "rho_L": rho_hat, "eps_mode": args.eps},
+                               f"eps {args.eps} (kappa band [{band[0]:g},{band[1]:g}], bisection to kappa_T={args.kappa:g}), "
+                               f"Schnakenberg FP32 RK4 x{args.rk4_steps}", "N": args.N, "n": n,
+                   "rk4_steps": args.rk4_steps, "rk4_dt": dt_rk4, "rho_L": rho_hat, "eps_mode": args.eps},
         "phases_ms": med,
         "roofline": roof_s if dominant_is_rk4 else roof_w,
         "roofline_other": roof_w if dominant_is_rk4 else roof_s,
@@ -232,6 +350,8 @@ def main():
                           {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
                           "median_log10_kappa": float(np.median(np.log10(kap)))},
         "state_finite": bool(np.isfinite(fin).all()),
+        "training": train_info,
+        "learned_vs_bisection": compare,
     }
     if not args.no_cpu_baseline:
         idx_h = idx.cpu().numpy()

@@ -169,6 +169,54 @@ int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int3
                const double* D, int32_t reaction, const double* params, double dt, int64_t nsteps,
                int32_t graph_steps);
 
+/* ------------------------------------------------------------------------
+ * Learned shape parameter.  A 128 -> 128 -> 128 -> 1 ReLU network maps a
+ * stencil's tangent-plane offsets to y = log(eps * rho) (rho = stencil
+ * radius), trained on eps found by the bisection of Sec. 5 (eq.
+ * target_cond).  Its proposal is checked by kappa_2 in
+ * rbffd_build_weights (RBFFD_EPS_LEARNED), with bisection as fallback.
+ * Parameters: one FP32 array of RBFFD_MLP_PARAMS values: W1[128][128]
+ * (out, in), b1[128], W2[128][128], b2[128], w3[128], b3.  Matrix products
+ * run on BF16 MFMA with FP32 accumulation; activations are rounded to BF16.
+ * ------------------------------------------------------------------------ */
+#define RBFFD_MLP_IN 128
+#define RBFFD_MLP_HIDDEN 128
+#define RBFFD_MLP_PARAMS 33153
+
+typedef struct {
+    double lr;        /* Adam step size */
+    double beta1;     /* Adam moment decays */
+    double beta2;
+    double adam_eps;
+    int32_t batch;    /* samples per step, a positive multiple of 64 */
+    int32_t steps;    /* optimiser steps in this call */
+    uint64_t seed;    /* non-zero; batch rows are drawn by a counter-based hash of (seed, step) */
+    int64_t step0;    /* index of the first step (Adam bias correction and sampling) */
+} rbffd_train_opts;
+
+/* Features of N stencils: feats is N x 128 BF16 (stored as uint16), row s =
+ * (s_2, t_2, s_3, t_3, ..., zero padding) with (s_j, t_j) the offsets
+ * x_j - x_1 in the tangent frame (tau_1 along the nearest neighbour's
+ * projected offset, tau_2 = nu x tau_1) divided by rho.  rho (nullable): N
+ * FP64 stencil radii.  Requires 2 <= n <= 65. */
+int rbffd_mlp_features(rbffd_ctx ctx, int64_t N, const double* xyz, const double* nrm, const int32_t* idx,
+                       int32_t n, uint16_t* feats, double* rho);
+/* y[B] (FP32) = network(feats[B x 128]). */
+int rbffd_mlp_forward(rbffd_ctx ctx, const float* params, int64_t B, const uint16_t* feats, float* y);
+/* Gradient of the mean squared error over all B samples: grad[RBFFD_MLP_PARAMS]
+ * (FP32, overwritten) and loss[1] (FP32, overwritten). */
+int rbffd_mlp_grad(rbffd_ctx ctx, const float* params, int64_t B, const uint16_t* feats, const float* target,
+                   float* grad, float* loss);
+/* Adam training on (feats, target) pairs (count samples); params, adam_m and
+ * adam_v (RBFFD_MLP_PARAMS FP32 each) are updated in place.  loss_per_step
+ * (nullable): opts->steps FP32 batch losses. */
+int rbffd_mlp_train(rbffd_ctx ctx, float* params, float* adam_m, float* adam_v, int64_t count,
+                    const uint16_t* feats, const float* target, const rbffd_train_opts* opts,
+                    float* loss_per_step);
+/* eps[N] (FP64) = exp(network(features)) / rho for the stencils idx. */
+int rbffd_predict_eps(rbffd_ctx ctx, const float* params, int64_t N, const double* xyz, const double* nrm,
+                      const int32_t* idx, int32_t n, double* eps);
+
 #ifdef __cplusplus
 }
 #endif

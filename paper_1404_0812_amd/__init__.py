@@ -222,3 +222,105 @@ class Operator:
                                                REACTIONS[reaction], prm, float(dt), int(nsteps), int(graph_steps)))
         self.ctx.leave()
         return st
+
+
+# ------------------------------------------------------------ learned eps ----
+
+MLP_IN = 128
+MLP_HIDDEN = 128
+MLP_PARAMS = _lib.MLP_PARAMS
+
+
+def mlp_init(seed=0, n_in=98, bias_out=0.0):
+    """He-uniform initial parameters (FP32 numpy); padded input columns are zero."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    H, F = MLP_HIDDEN, MLP_IN
+    W1 = np.zeros((H, F))
+    W1[:, :n_in] = rng.uniform(-1, 1, size=(H, n_in)) * np.sqrt(6.0 / n_in)
+    W2 = rng.uniform(-1, 1, size=(H, H)) * np.sqrt(6.0 / H)
+    w3 = rng.uniform(-1, 1, size=H) * np.sqrt(6.0 / H) * 0.1
+    p = np.concatenate([W1.ravel(), np.zeros(H), W2.ravel(), np.zeros(H), w3, [bias_out]])
+    assert p.size == MLP_PARAMS
+    return p.astype(np.float32)
+
+
+def mlp_features(xyz, nrm, idx, ctx=None):
+    """BF16 features (N x 128, stored as int16) and stencil radii (N, FP64)."""
+    ctx = ctx or default_context()
+    xyz = _dev(xyz, torch.float64, "xyz")
+    nrm = _dev(nrm, torch.float64, "nrm")
+    idx = _dev(idx, torch.int32, "idx")
+    N, n = idx.shape
+    feats = torch.empty((N, MLP_IN), dtype=torch.int16, device=xyz.device)
+    rho = torch.empty(N, dtype=torch.float64, device=xyz.device)
+    ctx.enter(xyz, nrm, idx, feats, rho)
+    ctx.check(ctx.lib.rbffd_mlp_features(ctx.h, N, _ptr(xyz), _ptr(nrm), _ptr(idx), n, _ptr(feats), _ptr(rho)))
+    ctx.leave()
+    return feats, rho
+
+
+def mlp_forward(params, feats, ctx=None):
+    ctx = ctx or default_context()
+    params = _dev(params, torch.float32, "params")
+    feats = _dev(feats, torch.int16, "feats")
+    y = torch.empty(feats.shape[0], dtype=torch.float32, device=feats.device)
+    ctx.enter(params, feats, y)
+    ctx.check(ctx.lib.rbffd_mlp_forward(ctx.h, _ptr(params), feats.shape[0], _ptr(feats), _ptr(y)))
+    ctx.leave()
+    return y
+
+
+def mlp_grad(params, feats, target, ctx=None):
+    ctx = ctx or default_context()
+    params = _dev(params, torch.float32, "params")
+    feats = _dev(feats, torch.int16, "feats")
+    target = _dev(target, torch.float32, "target")
+    g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=feats.device)
+    loss = torch.empty(1, dtype=torch.float32, device=feats.device)
+    ctx.enter(params, feats, target, g, loss)
+    ctx.check(ctx.lib.rbffd_mlp_grad(ctx.h, _ptr(params), feats.shape[0], _ptr(feats), _ptr(target), _ptr(g),
+                                     _ptr(loss)))
+    ctx.leave()
+    return g, loss
+
+
+class MLP:
+    """The shape-parameter regressor with its Adam state, on the device."""
+
+    def __init__(self, params, ctx=None):
+        self.ctx = ctx or default_context()
+        dev = torch.device("cuda", self.ctx.device.index)
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(dev).contiguous().clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+
+    def train(self, feats, target, steps, batch=4096, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, seed=1):
+        feats = _dev(feats, torch.int16, "feats")
+        target = _dev(target, torch.float32, "target")
+        o = _lib.TrainOpts(lr, betas[0], betas[1], eps, int(batch), int(steps), int(seed), int(self.step))
+        losses = torch.empty(max(1, steps), dtype=torch.float32, device=feats.device)
+        self.ctx.enter(self.params, self.m, self.v, feats, target, losses)
+        self.ctx.check(self.ctx.lib.rbffd_mlp_train(self.ctx.h, _ptr(self.params), _ptr(self.m), _ptr(self.v),
+                                                    feats.shape[0], _ptr(feats), _ptr(target), ctypes.byref(o),
+                                                    _ptr(losses)))
+        self.ctx.leave()
+        self.step += steps
+        return losses[:steps]
+
+    def forward(self, feats):
+        return mlp_forward(self.params, feats, ctx=self.ctx)
+
+    def predict_eps(self, xyz, nrm, idx):
+        xyz = _dev(xyz, torch.float64, "xyz")
+        nrm = _dev(nrm, torch.float64, "nrm")
+        idx = _dev(idx, torch.int32, "idx")
+        N, n = idx.shape
+        eps = torch.empty(N, dtype=torch.float64, device=xyz.device)
+        self.ctx.enter(self.params, xyz, nrm, idx, eps)
+        self.ctx.check(self.ctx.lib.rbffd_predict_eps(self.ctx.h, _ptr(self.params), N, _ptr(xyz), _ptr(nrm),
+                                                      _ptr(idx), n, _ptr(eps)))
+        self.ctx.leave()
+        return eps

@@ -32,6 +32,21 @@ class WeightOpts(ctypes.Structure):
     ]
 
 
+class TrainOpts(ctypes.Structure):
+    _fields_ = [
+        ("lr", c_double),
+        ("beta1", c_double),
+        ("beta2", c_double),
+        ("adam_eps", c_double),
+        ("batch", c_int32),
+        ("steps", c_int32),
+        ("seed", ctypes.c_uint64),
+        ("step0", c_int64),
+    ]
+
+
+MLP_PARAMS = 33153
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "rbffd_default_opts": (None, [ctypes.POINTER(WeightOpts)]),
@@ -50,6 +65,14 @@ SIGNATURES = {
     "rbffd_apply": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rbffd_step": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double), c_int32,
                              ctypes.POINTER(c_double), c_double, c_int64, c_int32]),
+    "rbffd_mlp_features": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
+                                     c_void_p]),
+    "rbffd_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),
+    "rbffd_mlp_grad": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "rbffd_mlp_train": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_void_p, c_void_p,
+                                  ctypes.POINTER(TrainOpts), c_void_p]),
+    "rbffd_predict_eps": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int32,
+                                    c_void_p]),
 }
 
 _LIB = None

@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librbffd.so")
 ARCH = os.environ.get("RBFFD_ARCH", "gfx950")
 
-SOURCES = ["context.cpp", "grid_knn.hip", "weights.hip", "step.hip"]
+SOURCES = ["context.cpp", "grid_knn.hip", "weights.hip", "step.hip", "mlp.hip"]
 
 # Packed FP32 instructions are disabled for all device code: the compiler
 # otherwise forms v_pk_* FP32 operations from scalar float code.
