@@ -112,6 +112,88 @@ def _oracle_chunk(args):
     return len(out)
 
 
+def batched_section(rb, ctx, kappa_T=1e12, count=64, diffusion_steps=1000, seed=5):
+    """Many-surface form: `count` seeded spheres, tori and ellipsoids (axes
+    U[0.5, 2], N log-uniform in [2k, 60k], n from {31, 50, 70, 101}); weights
+    by bisection to kappa_T in the autotuned persistent launches, against the
+    same work as one rbffd_build_weights call per surface; then FP32 heat
+    steps of all surfaces through the block-diagonal operator, replayed from
+    captured graphs, with one dt (the smallest stable one of the batch)."""
+    import torch
+
+    from synth import surface_batch
+
+    t0 = time.perf_counter()
+    meta = surface_batch(count, seed=seed)
+    surfs = [(torch.as_tensor(m["X"]).cuda(), torch.as_tensor(m["nrm"]).cuda(), int(m["n"])) for m in meta]
+    total = sum(int(s[0].shape[0]) for s in surfs)
+    print(f"[bench] batch of {count} surfaces, {total} nodes, ready in {time.perf_counter() - t0:.1f} s", flush=True)
+    st = ctx.stream
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(st)
+        return e
+
+    stencils = []
+    for X, _, n in surfs:
+        idx, perm = rb.knn(X, n, ctx=ctx)
+        stencils.append((idx, perm))
+    with_idx = [(X, nrm, n, stencils[i][0]) for i, (X, nrm, n) in enumerate(surfs)]
+    cache = os.path.join(os.environ.get("TMPDIR", "/tmp"), "rbffd_autotune.json")
+    t0 = time.perf_counter()
+    tuning = rb.autotune_batched(with_idx, cache_path=cache, retune=True, ctx=ctx, eps_mode="bisect",
+                                 kappa_target=kappa_T)
+    t_tune = time.perf_counter() - t0
+    print(f"[bench] autotune {t_tune:.1f} s: {tuning}", flush=True)
+    runs = []
+    for _ in range(2):
+        torch.cuda.synchronize()
+        a = ev()
+        res = rb.build_weights_batched(with_idx, tuning=tuning, ctx=ctx, eps_mode="bisect", kappa_target=kappa_T)
+        b = ev()
+        torch.cuda.synchronize()
+        runs.append(a.elapsed_time(b))
+    torch.cuda.synchronize()
+    a = ev()
+    for X, nrm, n, idx in with_idx:
+        rb.build_weights(X, nrm, n, idx=idx, ctx=ctx, eps_mode="bisect", kappa_target=kappa_T)
+    b = ev()
+    torch.cuda.synchronize()
+    per_surface_ms = a.elapsed_time(b)
+    ms = min(runs)
+    status = torch.cat([r.status for r in res]).cpu().numpy()
+    kap = torch.cat([r.kappa for r in res]).cpu().numpy()
+    print(f"[bench] batched weights {ms:.1f} ms ({total / ms * 1e3:.3g} stencils/s); one call per surface "
+          f"{per_surface_ms:.1f} ms", flush=True)
+    op = rb.Operator.batched([(r.idx, r.w, stencils[i][1]) for i, r in enumerate(res)], ctx=ctx)
+    rho = spectral_radius(op, total, iters=200)
+    dt = 0.5 * 2.785 / rho
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    u0 = torch.rand(total, dtype=torch.float64, device="cuda", generator=g)
+    op.step(u0, dt, 100, prec="f32", graph_steps=100)  # warm: capture the graph
+    torch.cuda.synchronize()
+    a = ev()
+    out = op.step(u0, dt, diffusion_steps, prec="f32", graph_steps=100)
+    b = ev()
+    torch.cuda.synchronize()
+    ms_step = a.elapsed_time(b) / diffusion_steps
+    slots = sum(int(s[0].shape[0]) * (s[2] - 1) for s in surfs)
+    step_bytes = 4 * slots * 8 + total * 4 * (3 + 5 + 5 + 4)
+    ns = {}
+    for _, _, n in surfs:
+        ns[str(n)] = ns.get(str(n), 0) + 1
+    del op
+    return {"surfaces": count, "stencils": total, "surfaces_per_n": ns, "kappa_target": kappa_T,
+            "tuning": tuning, "autotune_s": t_tune, "weights_ms": ms, "stencil_weights_per_s": total / ms * 1e3,
+            "per_surface_calls_ms": per_surface_ms, "speedup_vs_per_surface_calls": per_surface_ms / ms,
+            "status_counts": {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
+            "median_log10_kappa": float(np.median(np.log10(kap[np.isfinite(kap)]))),
+            "diffusion": {"steps": diffusion_steps, "dt": dt, "rho_L": rho, "prec": "f32",
+                          "ms_per_step": ms_step, "achieved_GBs": step_bytes / (ms_step / 1e3) / 1e9,
+                          "state_finite": bool(torch.isfinite(out).all().item())}}
+
+
 def training_sets(scale=1.0):
     """Seeded node sets for the labels (none of them is the benchmark blob):
     two Poisson-disk blobs with other centres, jittered tori and ellipsoids."""
@@ -144,6 +226,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -257,7 +340,7 @@ def main():
     roof_w = {"bound": "alu", "achieved": w_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
               "frac": w_tflops / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_weights (FP64 VALU)"}
     roof_s = {"bound": "hbm", "achieved": rk4_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rk4_stage (ELL SpMV + RK4)"}
+              "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rk4_stage (sliced-ELL SpMV + RK4)"}
     dominant_is_rk4 = med["rk4"] >= med["weights"]
 
     def growth_rate(w_tensor, idx_t, perm_t):
@@ -325,6 +408,10 @@ def main():
             lit["training"] = info_l
             compare = {"run_target": compare, "literal_target": lit}
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_section(rb, ctx)
+
     line = {
         "metric": "stencil weights/s + ms per RK4 step at N=1e6,n=50; learned-eps vs bisection",
         "value": value,
@@ -352,6 +439,7 @@ def main():
         "state_finite": bool(np.isfinite(fin).all()),
         "training": train_info,
         "learned_vs_bisection": compare,
+        "batched": batched,
     }
     if not args.no_cpu_baseline:
         idx_h = idx.cpu().numpy()

@@ -137,16 +137,97 @@ int rbffd_build_weights(rbffd_ctx ctx, int64_t N, const double* xyz, const doubl
 int rbffd_kappa(rbffd_ctx ctx, int64_t N, const double* xyz, const rbffd_weight_opts* opts,
                 const int32_t* idx, const double* eps_in, double* kappa);
 
+/* ------------------------------------------------------------------------
+ * Batched weights (Secs. 4 and 5 applied to many node sets at once).  The
+ * stencils of nsurf surfaces, each with its own N and n, are computed by
+ * persistent launches -- one for the surfaces with n + border <= 64 (one
+ * wavefront per stencil), one for 64 < n + border <= 128 (four wavefronts per
+ * stencil) -- whose workgroups take work items (runs of consecutive stencils
+ * of one surface) from an atomic counter until none are left.  Every output
+ * is bit-identical to rbffd_build_weights on that surface with the same opts
+ * and the surface's n.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t N;              /* nodes of this surface (0 allowed: skipped) */
+    int32_t n;              /* stencil size on this surface (opts->n is ignored) */
+    int32_t reserved;
+    const double* xyz;      /* N x 3 */
+    const double* nrm;      /* N x 3 */
+    const int32_t* idx;     /* N x n stencils, or NULL: computed into idx_out first */
+    const double* eps_in;   /* N, GIVEN/LEARNED modes */
+    int32_t* idx_out;       /* N x n, required when idx is NULL (nullable otherwise) */
+    double* w;              /* N x n output */
+    double* eps;            /* N outputs, nullable as in rbffd_build_weights */
+    double* kappa;
+    int32_t* status;
+    int32_t* nevals;
+} rbffd_surface;
+
+#define RBFFD_BUCKETS 2 /* tuning[0]: n + border <= 64; tuning[1]: 64 < n + border <= 128 */
+
+/* Schedule of one bucket's persistent launch. */
+typedef struct {
+    int32_t stencils_per_item; /* stencils taken per counter increment, 1..4096 */
+    int32_t groups_per_cu;     /* persistent workgroups (four wavefronts) per compute unit, 1 or 2 */
+    int32_t order;             /* 0: surfaces by decreasing n, ties as given; 1: as given */
+    int32_t reserved;
+    double us_per_stencil;     /* set by rbffd_autotune_batched: measured time per sampled stencil */
+} rbffd_batch_tuning;
+
+/* surf: HOST array of nsurf descriptors (device pointers inside).  tuning:
+ * HOST array of RBFFD_BUCKETS schedules, or NULL for the built-in default
+ * (16 stencils per item in bucket 0, 2 in bucket 1, 2 groups per CU, order 0).
+ * Errors: as rbffd_build_weights for any surface (the message names it);
+ * nsurf < 0; a schedule out of range. */
+int rbffd_build_weights_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_surface* surf,
+                                const rbffd_weight_opts* opts, const rbffd_batch_tuning* tuning);
+
+/* Autotuner for rbffd_build_weights_batched.  For each bucket that holds
+ * stencils, times every candidate schedule (stencils per item, groups per
+ * CU, order) on a sample of the batch (the first stencils of every surface
+ * in the bucket, about 32768 stencils in bucket 0 and 8192 in bucket 1) and
+ * writes the fastest to tuning[bucket] (HOST, RBFFD_BUCKETS entries; buckets
+ * without stencils get the default).  Results are cached per (GPU
+ * architecture, kernel, poly_degree, eps_mode, bucket) in memory and, when
+ * cache_path (HOST string, nullable) is given, in that JSON file, which is
+ * read first and rewritten with the new entries.  retune = 1 ignores cached
+ * entries.  The timing runs compute (and overwrite) the outputs of the
+ * sampled stencils; stencils are computed into idx_out first where idx is
+ * NULL.  The call synchronises the context's stream. */
+int rbffd_autotune_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_surface* surf,
+                           const rbffd_weight_opts* opts, const char* cache_path, int32_t retune,
+                           rbffd_batch_tuning* tuning);
+
 /*
  * Sparse operator L_X (Sec. 4: row k = weights of stencil k).  Built from
- * caller-order idx/w (N x n); stored internally in ELL slot-major form in the
- * spatial order `perm` (nullable: identity), in FP64 and, for FP32 stepping,
- * as FP32 off-diagonal weights for the difference form
- * sum_{j != i} w_ij (u_j - u_i).  *out is a HOST pointer.  The operator owns
- * device memory freed by rbffd_op_destroy.
+ * caller-order idx/w (N x n); stored internally as sliced ELL (slices of 64
+ * rows, slot-major within a slice) in the spatial order `perm` (nullable:
+ * identity), in FP64 and, for FP32 stepping, as FP32 off-diagonal weights
+ * for the difference form sum_{j != i} w_ij (u_j - u_i).  *out is a HOST
+ * pointer.  The operator owns device memory freed by rbffd_op_destroy.
+ * Errors: N < 1, n < 2, n > 128, n > N, null idx or w.
  */
 int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_t* idx, const double* w,
                     const int32_t* perm, rbffd_op* out);
+
+/* One surface of a batched operator. */
+typedef struct {
+    int64_t N;            /* rows (nodes) of the surface, >= 1 */
+    int32_t n;            /* stencil size, 2..128, <= N */
+    int32_t reserved;
+    const int32_t* idx;   /* N x n, local node indices 0..N-1 */
+    const double* w;      /* N x n weights */
+    const int32_t* perm;  /* N, spatial order of the surface (nullable: identity) */
+} rbffd_op_surface;
+
+/* Block-diagonal operator of nsurf surfaces with their own N and n: one
+ * rbffd_step then advances every surface with one kernel per RK4 stage (and
+ * one captured graph per batch of steps), with one dt for all (the caller
+ * passes the smallest stable dt of the surfaces).  State arrays hold the
+ * surfaces one after another: species s, node i of surface t at
+ * s * sum_N + (N_0 + ... + N_{t-1}) + i.  surf is a HOST array.
+ * Errors: nsurf < 1 or any surface invalid as in rbffd_op_create. */
+int rbffd_op_create_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_op_surface* surf, rbffd_op* out);
 int rbffd_op_destroy(rbffd_op op);
 
 /*

@@ -8,7 +8,9 @@ and make it wait for their results.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from dataclasses import dataclass
 
 import torch
@@ -52,12 +54,16 @@ class Context:
         if rc != 0:
             raise RbffdError(f"rbffd_create failed ({rc})")
         self.h = h
+        _LIVE_CTX.add(self)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rbffd_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
-            if getattr(self, "h", None):
-                self.lib.rbffd_destroy(self.h)
-                self.h = None
+            self.close()
         except Exception:
             pass
 
@@ -78,6 +84,24 @@ class Context:
 
 
 _DEFAULT = {}
+_LIVE_OPS = weakref.WeakSet()
+_LIVE_CTX = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    """Free operators, then contexts, while the HIP runtime is still up (the
+    order in which the interpreter would otherwise collect them is arbitrary)."""
+    for op in list(_LIVE_OPS):
+        try:
+            op.close()
+        except Exception:
+            pass
+    for c in list(_LIVE_CTX):
+        try:
+            c.close()
+        except Exception:
+            pass
 
 
 def default_context():
@@ -174,8 +198,86 @@ def kappa(xyz, idx, eps_in, n=None, ctx=None, **kw):
     return out
 
 
+# ---------------------------------------------------------------- batched ----
+
+def _tuning_array(tuning):
+    arr = (_lib.BatchTuning * _lib.BUCKETS)()
+    for b, t in enumerate(tuning):
+        arr[b].stencils_per_item = int(t["stencils_per_item"])
+        arr[b].groups_per_cu = int(t["groups_per_cu"])
+        arr[b].order = int(t["order"])
+        arr[b].us_per_stencil = float(t.get("us_per_stencil", 0.0))
+    return arr
+
+
+def _batch_surfaces(surfaces, eps_in, dev):
+    """Descriptors and output tensors of a batched build (surfaces: list of (xyz, nrm, n[, idx]))."""
+    descs = (_lib.Surface * len(surfaces))()
+    keep, outs = [], []
+    for s, surf in enumerate(surfaces):
+        xyz, nrm, n = surf[0], surf[1], int(surf[2])
+        idx = surf[3] if len(surf) > 3 else None
+        xyz = _dev(xyz, torch.float64, "xyz")
+        nrm = _dev(nrm, torch.float64, "nrm")
+        N = xyz.shape[0]
+        idx_in = _dev(idx, torch.int32, "idx") if idx is not None else None
+        e_in = _dev(eps_in[s], torch.float64, "eps_in") if eps_in is not None else None
+        idx_out = idx_in if idx_in is not None else torch.empty((N, n), dtype=torch.int32, device=dev)
+        r = Weights(idx_out, torch.empty((N, n), dtype=torch.float64, device=dev),
+                    torch.empty(N, dtype=torch.float64, device=dev), torch.empty(N, dtype=torch.float64, device=dev),
+                    torch.empty(N, dtype=torch.int32, device=dev), torch.empty(N, dtype=torch.int32, device=dev))
+        d = descs[s]
+        d.N, d.n = N, n
+        d.xyz, d.nrm = xyz.data_ptr(), nrm.data_ptr()
+        d.idx = idx_in.data_ptr() if idx_in is not None else None
+        d.eps_in = e_in.data_ptr() if e_in is not None else None
+        d.idx_out = idx_out.data_ptr() if idx_in is None else None
+        d.w, d.eps, d.kappa = r.w.data_ptr(), r.eps.data_ptr(), r.kappa.data_ptr()
+        d.status, d.nevals = r.status.data_ptr(), r.nevals.data_ptr()
+        keep += [xyz, nrm, idx_in, e_in, idx_out, r.w, r.eps, r.kappa, r.status, r.nevals]
+        outs.append(r)
+    return descs, keep, outs
+
+
+def autotune_batched(surfaces, eps_in=None, cache_path=None, retune=False, ctx=None, **kw):
+    """Schedules (one dict per bucket) chosen by the library's autotuner; see build_weights_batched."""
+    ctx = ctx or default_context()
+    o = make_opts(int(surfaces[0][2]) if surfaces else 31, **kw)
+    descs, keep, _ = _batch_surfaces(surfaces, eps_in, ctx.device)
+    out = (_lib.BatchTuning * _lib.BUCKETS)()
+    ctx.enter(*keep)
+    path = cache_path.encode() if cache_path else None
+    ctx.check(ctx.lib.rbffd_autotune_batched(ctx.h, len(surfaces), descs, ctypes.byref(o), path, int(bool(retune)),
+                                             out))
+    ctx.leave()
+    return [dict(stencils_per_item=t.stencils_per_item, groups_per_cu=t.groups_per_cu, order=t.order,
+                 us_per_stencil=t.us_per_stencil) for t in out]
+
+
+def build_weights_batched(surfaces, eps_in=None, tuning=None, ctx=None, **kw):
+    """Weights of many surfaces in persistent launches.
+
+    surfaces: list of (xyz, nrm, n) or (xyz, nrm, n, idx) with each surface's
+    own stencil size n; eps_in: per-surface eps tensors for given/learned
+    modes; tuning: per-bucket schedules from autotune_batched (None: the
+    library default).  Other keywords as make_opts (n is per surface).
+    Returns one Weights per surface."""
+    ctx = ctx or default_context()
+    o = make_opts(int(surfaces[0][2]) if surfaces else 31, **kw)
+    descs, keep, outs = _batch_surfaces(surfaces, eps_in, ctx.device)
+    tun = _tuning_array(tuning) if tuning is not None else None
+    ctx.enter(*keep)
+    ctx.check(ctx.lib.rbffd_build_weights_batched(ctx.h, len(surfaces), descs, ctypes.byref(o), tun))
+    ctx.leave()
+    return outs
+
+
 class Operator:
-    """Sparse L_X built from caller-order stencils and weights."""
+    """Sparse L_X built from caller-order stencils and weights.
+
+    Operator(idx, w, perm) holds one surface; Operator.batched([(idx, w,
+    perm), ...]) holds many (block-diagonal, state arrays concatenated by
+    surface)."""
 
     def __init__(self, idx, w, perm=None, ctx=None):
         self.ctx = ctx or default_context()
@@ -189,10 +291,36 @@ class Operator:
                                                     ctypes.byref(h)))
         self.ctx.leave()
         self.h = h
+        _LIVE_OPS.add(self)
+
+    @classmethod
+    def batched(cls, parts, ctx=None):
+        self = cls.__new__(cls)
+        self.ctx = ctx or default_context()
+        descs = (_lib.OpSurface * len(parts))()
+        keep = []
+        for s, part in enumerate(parts):
+            idx = _dev(part[0], torch.int32, "idx")
+            w = _dev(part[1], torch.float64, "w")
+            perm = _dev(part[2], torch.int32, "perm") if len(part) > 2 and part[2] is not None else None
+            descs[s].N, descs[s].n = idx.shape
+            descs[s].idx, descs[s].w = idx.data_ptr(), w.data_ptr()
+            descs[s].perm = perm.data_ptr() if perm is not None else None
+            keep += [idx, w, perm]
+        self.N = sum(int(d.N) for d in descs)
+        self.n = max(int(d.n) for d in descs)
+        h = ctypes.c_void_p()
+        self.ctx.enter(*keep)
+        self.ctx.check(self.ctx.lib.rbffd_op_create_batched(self.ctx.h, len(parts), descs, ctypes.byref(h)))
+        self.ctx.leave()
+        self.h = h
+        _LIVE_OPS.add(self)
+        return self
 
     def close(self):
         if getattr(self, "h", None):
-            self.ctx.lib.rbffd_op_destroy(self.h)
+            if getattr(self.ctx, "h", None):  # the context must still exist
+                self.ctx.lib.rbffd_op_destroy(self.h)
             self.h = None
 
     def __del__(self):

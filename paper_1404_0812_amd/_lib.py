@@ -45,6 +45,46 @@ class TrainOpts(ctypes.Structure):
     ]
 
 
+class Surface(ctypes.Structure):
+    _fields_ = [
+        ("N", c_int64),
+        ("n", c_int32),
+        ("reserved", c_int32),
+        ("xyz", c_void_p),
+        ("nrm", c_void_p),
+        ("idx", c_void_p),
+        ("eps_in", c_void_p),
+        ("idx_out", c_void_p),
+        ("w", c_void_p),
+        ("eps", c_void_p),
+        ("kappa", c_void_p),
+        ("status", c_void_p),
+        ("nevals", c_void_p),
+    ]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [
+        ("stencils_per_item", c_int32),
+        ("groups_per_cu", c_int32),
+        ("order", c_int32),
+        ("reserved", c_int32),
+        ("us_per_stencil", c_double),
+    ]
+
+
+class OpSurface(ctypes.Structure):
+    _fields_ = [
+        ("N", c_int64),
+        ("n", c_int32),
+        ("reserved", c_int32),
+        ("idx", c_void_p),
+        ("w", c_void_p),
+        ("perm", c_void_p),
+    ]
+
+
+BUCKETS = 2
 MLP_PARAMS = 33153
 
 # name -> (restype, argtypes)
@@ -62,6 +102,11 @@ SIGNATURES = {
     "rbffd_op_create": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p,
                                   ctypes.POINTER(c_void_p)]),
     "rbffd_op_destroy": (c_int32, [c_void_p]),
+    "rbffd_op_create_batched": (c_int32, [c_void_p, c_int32, ctypes.POINTER(OpSurface), ctypes.POINTER(c_void_p)]),
+    "rbffd_build_weights_batched": (c_int32, [c_void_p, c_int32, ctypes.POINTER(Surface), ctypes.POINTER(WeightOpts),
+                                              ctypes.POINTER(BatchTuning)]),
+    "rbffd_autotune_batched": (c_int32, [c_void_p, c_int32, ctypes.POINTER(Surface), ctypes.POINTER(WeightOpts),
+                                         ctypes.c_char_p, c_int32, ctypes.POINTER(BatchTuning)]),
     "rbffd_apply": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rbffd_step": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double), c_int32,
                              ctypes.POINTER(c_double), c_double, c_int64, c_int32]),

@@ -17,11 +17,21 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "librbffd.so")
 ARCH = os.environ.get("RBFFD_ARCH", "gfx950")
 
-SOURCES = ["context.cpp", "grid_knn.hip", "weights.hip", "step.hip", "mlp.hip"]
+# (source, object name, defines); the weights kernels are built once per
+# (radial kernel, tiling) so that the six large variants compile in parallel.
+# Longest first.
+SOURCES = [("weights_kernels.hip", f"weights_k{k}_nb{nb}", [f"-DRBW_K={k}", f"-DRBW_NB={nb}"])
+           for nb in (2, 1) for k in (0, 1, 2)]
+SOURCES += [("mlp.hip", "mlp", []), ("step.hip", "step", []), ("grid_knn.hip", "grid_knn", []),
+            ("context.cpp", "context", []), ("batched.cpp", "batched", []), ("weights.cpp", "weights", [])]
 
 # Packed FP32 instructions are disabled for all device code: the compiler
 # otherwise forms v_pk_* FP32 operations from scalar float code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# The weights kernels keep the local matrix in registers and index it only
+# with loop counters of fully unrolled loops; the default size limit of a
+# full unroll would leave the largest loops rolled and the matrix in scratch.
+UNROLL_FLAGS = ["-mllvm", "-pragma-unroll-threshold=200000"]
 
 
 def hipcc():
@@ -31,12 +41,13 @@ def hipcc():
     return "hipcc"
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(entry, verbose: bool) -> str:
+    src, name, defines = entry
+    obj = os.path.join(BUILD, name + ".o")
     cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC]
-    cmd += DEVICE_FLAGS
+    cmd += DEVICE_FLAGS + defines
     if src.endswith(".hip"):
-        cmd += ["-munsafe-fp-atomics"]
+        cmd += ["-munsafe-fp-atomics"] + UNROLL_FLAGS
         if os.environ.get("RBFFD_RESOURCE_USAGE"):
             cmd += ["-Rpass-analysis=kernel-resource-usage"]
         cmd += ["-x", "hip"]

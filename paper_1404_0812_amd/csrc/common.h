@@ -17,17 +17,32 @@ struct rbffd_ctx_s {
     // growable scratch owned by the context
     void* scratch = nullptr;
     size_t scratch_bytes = 0;
+    // work list of the batched weights launch (kept apart from scratch, which kNN uses)
+    void* batch = nullptr;
+    size_t batch_bytes = 0;
+};
+
+// One slice of the operator: 64 consecutive internal rows of one surface.
+struct OpSlice {
+    int64_t off64;  // element offset of the slice's slot 0 in the FP64 arrays (n slots)
+    int64_t off32;  // element offset in the FP32 off-diagonal arrays (n - 1 slots)
+    int32_t n;      // stencil size of the slice's rows
+    int32_t rows;   // rows in use (64 except at a surface's end)
 };
 
 struct rbffd_op_s {
     rbffd_ctx ctx = nullptr;
-    int64_t N = 0;
-    int32_t n = 0;
-    int32_t* ell_idx = nullptr;   // (n-1) x N slot-major, internal order, off-diagonal slots
-    float* ell_w32 = nullptr;     // (n-1) x N FP32 off-diagonal weights
-    double* ell_w64 = nullptr;    // n x N slot-major FP64 weights (slot 0 = centre)
-    int32_t* ell_idx64 = nullptr; // n x N slot-major, slot 0 = centre (internal order)
-    int32_t* perm = nullptr;      // internal position -> caller index
+    int64_t N = 0;        // rows in caller order (sum over surfaces)
+    int64_t P = 0;        // internal rows, each surface padded to a multiple of 64
+    int32_t n = 0;        // largest stencil size
+    int32_t nsurf = 0;
+    int64_t nslices = 0;
+    OpSlice* slices = nullptr;    // device, nslices
+    int32_t* idx64 = nullptr;     // FP64 form: slot k of row (slice, r) at off64 + 64 k + r, slot 0 = centre
+    double* w64 = nullptr;
+    int32_t* idx32 = nullptr;     // FP32 difference form: off-diagonal slots 1..n-1 at off32 + 64 (k-1) + r
+    float* w32 = nullptr;
+    int32_t* perm = nullptr;      // internal row -> caller row (-1 for padding), P entries
     // state workspace (internal order), allocated on first step
     void* work = nullptr;
     size_t work_bytes = 0;

@@ -71,6 +71,10 @@ extern "C" int rbffd_destroy(rbffd_ctx ctx) {
         (void)hipStreamSynchronize(ctx->stream);
         (void)hipFree(ctx->scratch);
     }
+    if (ctx->batch) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->batch);
+    }
     delete ctx;
     return RBFFD_OK;
 }

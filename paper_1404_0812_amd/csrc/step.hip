@@ -1,10 +1,14 @@
 // Sparse operator L_X and the method-of-lines time stepper (Sec. 4.2,
 // eq. kernel_mol): du_s/dt = D_s L_X u_s + R_s(u), classical RK4.
 //
-// Layout: ELL, slot-major (slot k of all rows contiguous), rows in the
-// library's spatial order, so that the loads of the weights and indices are
-// coalesced across a wavefront and the gathered neighbour values are close in
-// memory.  Every row has exactly n entries (Sec. 4), so there is no padding.
+// Layout: sliced ELL with slices of 64 rows (one wavefront), slot-major
+// inside a slice: slot k of row r of a slice sits at off + 64 k + r, so the
+// loads of the weights and indices of one wavefront are one contiguous run.
+// Every row of a surface has exactly n entries (Sec. 4), so a slice holds no
+// padding except past a surface's last row.  Rows are in the library's
+// spatial order, so the gathered neighbour values are close in memory.  Many
+// surfaces (each with its own N and n) form one block-diagonal operator:
+// each surface starts on a fresh slice and each slice carries its own n.
 // FP64 state uses the plain form sum_j w_ij u_j over all n slots.  FP32 state
 // uses the difference form sum_{j != i} w_ij (u_j - u_i) with FP32 weights;
 // it equals L u because the rows of L_X sum to zero (constants are
@@ -16,53 +20,66 @@
 // steps are captured in a HIP graph and replayed.
 #include "common.h"
 
+#include <algorithm>
 #include <cstring>
+#include <new>
+#include <vector>
 
 namespace {
 
 constexpr int BLK = 256;
 
+// iperm[perm[p]] = p for one surface (perm nullable: identity)
 __global__ void k_inverse_perm(int64_t N, const int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p < N) iperm[perm ? perm[p] : p] = (int32_t)p;
 }
 
-__global__ void k_build_ell(int64_t N, int n, const int32_t* __restrict__ idx, const double* __restrict__ w,
-                            const int32_t* __restrict__ perm, const int32_t* __restrict__ iperm,
-                            int32_t* __restrict__ ell_idx64, double* __restrict__ ell_w64,
-                            int32_t* __restrict__ ell_idx, float* __restrict__ ell_w32) {
+// Rows of one surface into the slices.  row0: first internal row of the
+// surface, col0: its first caller row; gperm: internal row -> caller row.
+__global__ void k_build_sell(int64_t N, int n, int64_t row0, int64_t col0, const int32_t* __restrict__ idx,
+                             const double* __restrict__ w, const int32_t* __restrict__ perm,
+                             const int32_t* __restrict__ iperm, const OpSlice* __restrict__ slices,
+                             int32_t* __restrict__ idx64, double* __restrict__ w64, int32_t* __restrict__ idx32,
+                             float* __restrict__ w32, int32_t* __restrict__ gperm) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= N) return;
-    int64_t i = perm ? perm[p] : p;
+    const int64_t i = perm ? perm[p] : p;
+    const int64_t q = row0 + p;
+    const OpSlice sl = slices[q >> 6];
+    const int r = (int)(q & 63);
     for (int k = 0; k < n; ++k) {
-        int j = iperm[idx[i * n + k]];
-        double wk = w[i * n + k];
-        ell_idx64[(int64_t)k * N + p] = j;
-        ell_w64[(int64_t)k * N + p] = wk;
+        const int32_t j = (int32_t)(row0 + iperm[idx[i * n + k]]);
+        const double wk = w[i * n + k];
+        idx64[sl.off64 + 64 * k + r] = j;
+        w64[sl.off64 + 64 * k + r] = wk;
         if (k > 0) {
-            ell_idx[(int64_t)(k - 1) * N + p] = j;
-            ell_w32[(int64_t)(k - 1) * N + p] = (float)wk;
+            idx32[sl.off32 + 64 * (k - 1) + r] = j;
+            w32[sl.off32 + 64 * (k - 1) + r] = (float)wk;
         }
     }
+    gperm[q] = (int32_t)(col0 + i);
 }
 
 // State lives species-interleaved in internal order: element (p, s) at p*S + s,
 // so that one gather fetches every species of a neighbour.
+// P internal rows, N caller rows; padding rows (perm -1) hold zero.
 template <typename T>
-__global__ void k_load_state(int64_t N, int S, const double* __restrict__ in, const int32_t* __restrict__ perm,
-                             T* __restrict__ out) {
+__global__ void k_load_state(int64_t P, int64_t N, int S, const double* __restrict__ in,
+                             const int32_t* __restrict__ perm, T* __restrict__ out) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    int64_t i = perm ? perm[p] : p;
-    for (int s = 0; s < S; ++s) out[p * S + s] = (T)in[s * N + i];
+    if (p >= P) return;
+    const int64_t i = perm[p];
+    for (int s = 0; s < S; ++s) out[p * S + s] = i >= 0 ? (T)in[s * N + i] : (T)0;
 }
 
 template <typename T>
-__global__ void k_store_state(int64_t N, int S, const T* __restrict__ in, const int32_t* __restrict__ perm,
+__global__ void k_store_state(int64_t P, int64_t N, int S, const T* __restrict__ in, const int32_t* __restrict__ perm,
                               double* __restrict__ out) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    int64_t i = perm ? perm[p] : p;
+    if (p >= P) return;
+    const int64_t i = perm[p];
+    if (i < 0) return;
     for (int s = 0; s < S; ++s) out[s * N + i] = (double)in[p * S + s];
 }
 
@@ -89,8 +106,8 @@ __device__ __forceinline__ void reaction(const T (&y)[2], T (&r)[2], const React
 }
 
 struct StageArgs {
-    int64_t N;
-    int nslots;       // slots read per row (n-1 for FP32 difference form, n for FP64)
+    int64_t nslices;
+    const OpSlice* slices;
     double D[2];
     double dt;
     ReactParams rp;
@@ -141,14 +158,42 @@ __device__ __forceinline__ void vstore(T* __restrict__ Y, int64_t j, const T (&v
 
 constexpr int CHUNK = 8;
 
-// L applied to the stage input of row p.  FP32: difference form over the n-1
-// off-diagonal slots; FP64: plain form over all n slots in slot order.
+// Row of the calling thread: slice and lane.  Four slices per 256-thread block.
+struct RowPos {
+    int64_t p;    // internal row
+    int64_t off;  // element offset of the row's slot 0 (precision's array)
+    int ns;       // slots to read
+    bool live;
+};
+
+template <typename T>
+__device__ __forceinline__ RowPos row_pos(const StageArgs& a) {
+    RowPos rp;
+    const int64_t slice = (int64_t)xcd_block() * (BLK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    rp.p = slice * 64 + lane;
+    rp.live = false;
+    rp.off = 0;
+    rp.ns = 0;
+    if (slice >= a.nslices) return rp;
+    const OpSlice sl = a.slices[slice];
+    if (lane >= sl.rows) return rp;
+    constexpr bool f32 = sizeof(T) == 4;
+    rp.live = true;
+    rp.off = (f32 ? sl.off32 : sl.off64) + lane;
+    rp.ns = f32 ? sl.n - 1 : sl.n;
+    return rp;
+}
+
+// L applied to the stage input of row rp.p.  FP32: difference form over the
+// n-1 off-diagonal slots; FP64: plain form over all n slots in slot order.
 template <typename T, int S>
-__device__ __forceinline__ void apply_row(const StageArgs& a, const int32_t* __restrict__ idx,
-                                          const T* __restrict__ w, const T* __restrict__ Y, int64_t p,
-                                          const T (&yi)[2], T (&acc)[2]) {
-    const int64_t N = a.N;
-    const int ns = a.nslots;
+__device__ __forceinline__ void apply_row(const RowPos& rp, const int32_t* __restrict__ idx,
+                                          const T* __restrict__ w, const T* __restrict__ Y, const T (&yi)[2],
+                                          T (&acc)[2]) {
+    const int ns = rp.ns;
+    const int32_t* ix = idx + rp.off;
+    const T* wx = w + rp.off;
     constexpr bool diff = sizeof(T) == 4;
     T s0 = 0, s1 = 0;
     int k0 = 0;
@@ -157,8 +202,8 @@ __device__ __forceinline__ void apply_row(const StageArgs& a, const int32_t* __r
         T wk[CHUNK];
 #pragma unroll
         for (int t = 0; t < CHUNK; ++t) {
-            j[t] = __builtin_nontemporal_load(idx + (int64_t)(k0 + t) * N + p);
-            wk[t] = __builtin_nontemporal_load(w + (int64_t)(k0 + t) * N + p);
+            j[t] = __builtin_nontemporal_load(ix + 64 * (k0 + t));
+            wk[t] = __builtin_nontemporal_load(wx + 64 * (k0 + t));
         }
 #pragma unroll
         for (int t = 0; t < CHUNK; ++t) {
@@ -174,8 +219,8 @@ __device__ __forceinline__ void apply_row(const StageArgs& a, const int32_t* __r
         }
     }
     for (int k = k0; k < ns; ++k) {
-        const int j = __builtin_nontemporal_load(idx + (int64_t)k * N + p);
-        const T wk = __builtin_nontemporal_load(w + (int64_t)k * N + p);
+        const int j = __builtin_nontemporal_load(ix + 64 * k);
+        const T wk = __builtin_nontemporal_load(wx + 64 * k);
         T y[2];
         vload<T, S>(Y, j, y);
         if (diff) {
@@ -196,12 +241,13 @@ template <typename T, int S, int R, int ST>
 __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* __restrict__ idx,
                                                    const T* __restrict__ w, const T* __restrict__ Y,
                                                    T* __restrict__ U, T* __restrict__ ACC, T* __restrict__ YN) {
-    const int64_t p = xcd_block() * BLK + threadIdx.x;
-    if (p >= a.N) return;
+    const RowPos rp = row_pos<T>(a);
+    if (!rp.live) return;
+    const int64_t p = rp.p;
     T yi[2];
     vload<T, S>(Y, p, yi);
     T lap[2];
-    apply_row<T, S>(a, idx, w, Y, p, yi, lap);
+    apply_row<T, S>(rp, idx, w, Y, yi, lap);
     T r[2];
     reaction<T, R>(yi, r, a.rp);
     T k[2];
@@ -238,18 +284,21 @@ __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* _
 template <typename T>
 __global__ __launch_bounds__(BLK) void k_apply(StageArgs a, const int32_t* __restrict__ idx, const T* __restrict__ w,
                                                const T* __restrict__ Y, T* __restrict__ out) {
-    const int64_t p = xcd_block() * BLK + threadIdx.x;
-    if (p >= a.N) return;
+    const RowPos rp = row_pos<T>(a);
+    if (!rp.live) return;
     T yi[2];
-    vload<T, 1>(Y, p, yi);
+    vload<T, 1>(Y, rp.p, yi);
     T lap[2];
-    apply_row<T, 1>(a, idx, w, Y, p, yi, lap);
-    out[p] = lap[0];
+    apply_row<T, 1>(rp, idx, w, Y, yi, lap);
+    out[rp.p] = lap[0];
 }
+
+// blocks of one stage launch: four slices each
+inline dim3 stage_grid(int64_t nslices) { return dim3((unsigned)((nslices + BLK / 64 - 1) / (BLK / 64))); }
 
 template <typename T, int S, int R>
 void enqueue_step(hipStream_t st, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC, T* Y1, T* Y2) {
-    const dim3 g((unsigned)((a.N + BLK - 1) / BLK)), b(BLK);
+    const dim3 g = stage_grid(a.nslices), b(BLK);
     hipLaunchKernelGGL((k_rk4_stage<T, S, R, 0>), g, b, 0, st, a, idx, w, U, U, ACC, Y1);
     hipLaunchKernelGGL((k_rk4_stage<T, S, R, 1>), g, b, 0, st, a, idx, w, Y1, U, ACC, Y2);
     hipLaunchKernelGGL((k_rk4_stage<T, S, R, 2>), g, b, 0, st, a, idx, w, Y2, U, ACC, Y1);
@@ -274,7 +323,7 @@ void enqueue_steps_t(hipStream_t st, int S, int R, const StageArgs& a, const int
 
 int ensure_work(rbffd_op op) {
     // 4 buffers (U, ACC, Y1, Y2) x 2 species x FP64
-    size_t need = 4 * 2 * (size_t)op->N * sizeof(double);
+    size_t need = 4 * 2 * (size_t)op->P * sizeof(double);
     if (op->work_bytes >= need) return RBFFD_OK;
     if (op->work) {
         (void)hipStreamSynchronize(op->ctx->stream);
@@ -297,45 +346,69 @@ void reset_graph(rbffd_op op) {
     op->graph_key_species = -1;
 }
 
-}  // namespace
-
-extern "C" int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_t* idx, const double* w,
-                               const int32_t* perm, rbffd_op* out) {
-    if (!ctx || !out) return RBFFD_E_ARG;
-    if (N <= 0 || N > 0x7fffffffLL) return set_error(ctx, RBFFD_E_ARG, "N out of range");
-    if (n < 2 || n > 128 || n > N) return set_error(ctx, RBFFD_E_ARG, "stencil size n=%d invalid", n);
-    if (!idx || !w) return set_error(ctx, RBFFD_E_ARG, "null pointer");
+// Build the sliced operator of nsurf surfaces (validated by the callers).
+int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* out) {
+    std::vector<OpSlice> sl;
+    std::vector<int64_t> row0(nsurf), col0(nsurf);
+    int64_t P = 0, N = 0, off64 = 0, off32 = 0, maxN = 0;
+    int32_t nmax = 0;
+    for (int s = 0; s < nsurf; ++s) {
+        row0[s] = P;
+        col0[s] = N;
+        const int64_t Ns = surf[s].N;
+        const int n = surf[s].n;
+        for (int64_t r = 0; r < Ns; r += 64) {
+            OpSlice o;
+            o.off64 = off64;
+            o.off32 = off32;
+            o.n = n;
+            o.rows = (int32_t)std::min<int64_t>(64, Ns - r);
+            sl.push_back(o);
+            off64 += 64 * (int64_t)n;
+            off32 += 64 * (int64_t)(n - 1);
+        }
+        P += (Ns + 63) / 64 * 64;
+        N += Ns;
+        maxN = std::max(maxN, Ns);
+        nmax = std::max(nmax, n);
+    }
+    if (P > 0x7fffffffLL) return set_error(ctx, RBFFD_E_ARG, "operator too large: %lld rows", (long long)P);
     rbffd_op op = new (std::nothrow) rbffd_op_s();
     if (!op) return set_error(ctx, RBFFD_E_NOMEM, "host allocation failed");
     op->ctx = ctx;
     op->N = N;
-    op->n = n;
-    const size_t Nn = (size_t)N * n, Nm = (size_t)N * (n - 1);
-    bool ok = hipMalloc(&op->ell_idx64, Nn * sizeof(int32_t)) == hipSuccess &&
-              hipMalloc(&op->ell_w64, Nn * sizeof(double)) == hipSuccess &&
-              hipMalloc(&op->ell_idx, Nm * sizeof(int32_t)) == hipSuccess &&
-              hipMalloc(&op->ell_w32, Nm * sizeof(float)) == hipSuccess &&
-              hipMalloc(&op->perm, (size_t)N * sizeof(int32_t)) == hipSuccess;
+    op->P = P;
+    op->n = nmax;
+    op->nsurf = nsurf;
+    op->nslices = (int64_t)sl.size();
+    bool ok = hipMalloc(&op->slices, std::max<size_t>(1, sl.size()) * sizeof(OpSlice)) == hipSuccess &&
+              hipMalloc(&op->idx64, std::max<int64_t>(1, off64) * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&op->w64, std::max<int64_t>(1, off64) * sizeof(double)) == hipSuccess &&
+              hipMalloc(&op->idx32, std::max<int64_t>(1, off32) * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&op->w32, std::max<int64_t>(1, off32) * sizeof(float)) == hipSuccess &&
+              hipMalloc(&op->perm, std::max<int64_t>(1, P) * sizeof(int32_t)) == hipSuccess;
     int32_t* iperm = nullptr;
-    ok = ok && hipMalloc(&iperm, (size_t)N * sizeof(int32_t)) == hipSuccess;
+    ok = ok && hipMalloc(&iperm, std::max<int64_t>(1, maxN) * sizeof(int32_t)) == hipSuccess;
     if (!ok) {
         rbffd_op_destroy(op);
         if (iperm) (void)hipFree(iperm);
         return set_error(ctx, RBFFD_E_NOMEM, "operator allocation failed");
     }
     hipStream_t st = ctx->stream;
-    const dim3 g((unsigned)((N + BLK - 1) / BLK)), b(BLK);
-    hipLaunchKernelGGL(k_inverse_perm, g, b, 0, st, N, perm, iperm);
-    hipLaunchKernelGGL(k_build_ell, g, b, 0, st, N, n, idx, w, perm, iperm, op->ell_idx64, op->ell_w64, op->ell_idx,
-                       op->ell_w32);
-    if (perm) {
-        (void)hipMemcpyAsync(op->perm, perm, (size_t)N * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
-    } else {
-        (void)hipFree(op->perm);
-        op->perm = nullptr;
+    hipError_t e = hipMemcpyAsync(op->slices, sl.data(), sl.size() * sizeof(OpSlice), hipMemcpyHostToDevice, st);
+    // padding rows: perm -1; their slots are never read (rows >= OpSlice::rows are skipped)
+    if (e == hipSuccess) e = hipMemsetAsync(op->perm, 0xff, (size_t)P * sizeof(int32_t), st);
+    for (int s = 0; s < nsurf && e == hipSuccess; ++s) {
+        const int64_t Ns = surf[s].N;
+        const dim3 g((unsigned)((Ns + BLK - 1) / BLK)), b(BLK);
+        hipLaunchKernelGGL(k_inverse_perm, g, b, 0, st, Ns, surf[s].perm, iperm);
+        hipLaunchKernelGGL(k_build_sell, g, b, 0, st, Ns, surf[s].n, row0[s], col0[s], surf[s].idx, surf[s].w,
+                           surf[s].perm, iperm, op->slices, op->idx64, op->w64, op->idx32, op->w32, op->perm);
+        e = hipGetLastError();
     }
-    hipError_t e = hipGetLastError();
-    (void)hipStreamSynchronize(st);
+    // the slice table comes from pageable host memory and iperm is reused per surface: wait here
+    const hipError_t e2 = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = e2;
     (void)hipFree(iperm);
     if (e != hipSuccess) {
         rbffd_op_destroy(op);
@@ -345,14 +418,51 @@ extern "C" int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_
     return RBFFD_OK;
 }
 
+int check_surface(rbffd_ctx ctx, int s, const rbffd_op_surface& d) {
+    if (d.N <= 0 || d.N > 0x7fffffffLL) return set_error(ctx, RBFFD_E_ARG, "surface %d: N out of range", s);
+    if (d.n < 2 || d.n > 128 || d.n > d.N)
+        return set_error(ctx, RBFFD_E_ARG, "surface %d: stencil size n=%d invalid", s, d.n);
+    if (!d.idx || !d.w) return set_error(ctx, RBFFD_E_ARG, "surface %d: null pointer", s);
+    return RBFFD_OK;
+}
+
+}  // namespace
+
+extern "C" int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_t* idx, const double* w,
+                               const int32_t* perm, rbffd_op* out) {
+    if (!ctx || !out) return RBFFD_E_ARG;
+    rbffd_op_surface d;
+    d.N = N;
+    d.n = n;
+    d.reserved = 0;
+    d.idx = idx;
+    d.w = w;
+    d.perm = perm;
+    if (N <= 0 || N > 0x7fffffffLL) return set_error(ctx, RBFFD_E_ARG, "N out of range");
+    if (n < 2 || n > 128 || n > N) return set_error(ctx, RBFFD_E_ARG, "stencil size n=%d invalid", n);
+    if (!idx || !w) return set_error(ctx, RBFFD_E_ARG, "null pointer");
+    return create_op(ctx, 1, &d, out);
+}
+
+extern "C" int rbffd_op_create_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_op_surface* surf, rbffd_op* out) {
+    if (!ctx || !out) return RBFFD_E_ARG;
+    if (nsurf < 1 || !surf) return set_error(ctx, RBFFD_E_ARG, "need at least one surface");
+    for (int s = 0; s < nsurf; ++s) {
+        int rc = check_surface(ctx, s, surf[s]);
+        if (rc) return rc;
+    }
+    return create_op(ctx, nsurf, surf, out);
+}
+
 extern "C" int rbffd_op_destroy(rbffd_op op) {
     if (!op) return RBFFD_E_ARG;
     if (op->ctx) (void)hipStreamSynchronize(op->ctx->stream);
     reset_graph(op);
-    if (op->ell_idx64) (void)hipFree(op->ell_idx64);
-    if (op->ell_w64) (void)hipFree(op->ell_w64);
-    if (op->ell_idx) (void)hipFree(op->ell_idx);
-    if (op->ell_w32) (void)hipFree(op->ell_w32);
+    if (op->slices) (void)hipFree(op->slices);
+    if (op->idx64) (void)hipFree(op->idx64);
+    if (op->w64) (void)hipFree(op->w64);
+    if (op->idx32) (void)hipFree(op->idx32);
+    if (op->w32) (void)hipFree(op->w32);
     if (op->perm) (void)hipFree(op->perm);
     if (op->work) (void)hipFree(op->work);
     delete op;
@@ -366,25 +476,24 @@ extern "C" int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const doubl
     int rc = ensure_work(op);
     if (rc) return rc;
     hipStream_t st = ctx->stream;
-    const int64_t N = op->N;
-    const dim3 g((unsigned)((N + BLK - 1) / BLK)), b(BLK);
+    const int64_t N = op->N, P = op->P;
+    const dim3 g((unsigned)((P + BLK - 1) / BLK)), b(BLK);
     StageArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.N = N;
+    a.nslices = op->nslices;
+    a.slices = op->slices;
     if (prec == RBFFD_F64) {
         double* Y = (double*)op->work;
-        double* out = Y + N;
-        a.nslots = op->n;
-        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, N, 1, u, op->perm, Y);
-        hipLaunchKernelGGL(k_apply<double>, g, b, 0, st, a, op->ell_idx64, op->ell_w64, Y, out);
-        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, N, 1, out, op->perm, Lu);
+        double* out = Y + P;
+        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, 1, u, op->perm, Y);
+        hipLaunchKernelGGL(k_apply<double>, stage_grid(a.nslices), b, 0, st, a, op->idx64, op->w64, Y, out);
+        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, P, N, 1, out, op->perm, Lu);
     } else {
         float* Y = (float*)op->work;
-        float* out = Y + N;
-        a.nslots = op->n - 1;
-        hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, N, 1, u, op->perm, Y);
-        hipLaunchKernelGGL(k_apply<float>, g, b, 0, st, a, op->ell_idx, op->ell_w32, Y, out);
-        hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, N, 1, out, op->perm, Lu);
+        float* out = Y + P;
+        hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, P, N, 1, u, op->perm, Y);
+        hipLaunchKernelGGL(k_apply<float>, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w32, Y, out);
+        hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, P, N, 1, out, op->perm, Lu);
     }
     HIP_TRY(ctx, hipGetLastError());
     return RBFFD_OK;
@@ -406,11 +515,12 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     int rc = ensure_work(op);
     if (rc) return rc;
     hipStream_t st = ctx->stream;
-    const int64_t N = op->N;
-    const dim3 g((unsigned)((N + BLK - 1) / BLK)), b(BLK);
+    const int64_t N = op->N, P = op->P;
+    const dim3 g((unsigned)((P + BLK - 1) / BLK)), b(BLK);
     StageArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.N = N;
+    a.nslices = op->nslices;
+    a.slices = op->slices;
     a.D[0] = D[0];
     a.D[1] = nspecies == 2 ? D[1] : 0.0;
     a.dt = dt;
@@ -420,16 +530,15 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     const size_t esz = prec == RBFFD_F64 ? sizeof(double) : sizeof(float);
     char* base = (char*)op->work;
     void* U = base;
-    void* ACC = base + 2 * N * esz;
-    void* Y1 = base + 4 * N * esz;
-    void* Y2 = base + 6 * N * esz;
-    const int32_t* idx = prec == RBFFD_F64 ? op->ell_idx64 : op->ell_idx;
-    const void* w = prec == RBFFD_F64 ? (const void*)op->ell_w64 : (const void*)op->ell_w32;
-    a.nslots = prec == RBFFD_F64 ? op->n : op->n - 1;
+    void* ACC = base + 2 * P * esz;
+    void* Y1 = base + 4 * P * esz;
+    void* Y2 = base + 6 * P * esz;
+    const int32_t* idx = prec == RBFFD_F64 ? op->idx64 : op->idx32;
+    const void* w = prec == RBFFD_F64 ? (const void*)op->w64 : (const void*)op->w32;
     if (prec == RBFFD_F64)
-        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, N, nspecies, state, op->perm, (double*)U);
+        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, nspecies, state, op->perm, (double*)U);
     else
-        hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, N, nspecies, state, op->perm, (float*)U);
+        hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, P, N, nspecies, state, op->perm, (float*)U);
     HIP_TRY(ctx, hipGetLastError());
 
     auto enqueue = [&](hipStream_t s, int64_t steps) {
@@ -473,9 +582,9 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     }
     if (rest > 0) enqueue(st, rest);
     if (prec == RBFFD_F64)
-        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, N, nspecies, (const double*)U, op->perm, state);
+        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, P, N, nspecies, (const double*)U, op->perm, state);
     else
-        hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, N, nspecies, (const float*)U, op->perm, state);
+        hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, P, N, nspecies, (const float*)U, op->perm, state);
     HIP_TRY(ctx, hipGetLastError());
     return RBFFD_OK;
 }

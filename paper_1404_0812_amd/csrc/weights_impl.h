@@ -1,0 +1,876 @@
+// Device routines of the per-stencil weights computation (see weights.hip).
+#pragma once
+
+#include "common.h"
+#include "weights_job.h"
+
+#include <cmath>
+
+namespace rbw {
+
+constexpr int RMAX = RBW_RMAX;  // border columns (degree-2 monomials in R^3)
+constexpr int CH = 4;            // rows per guarded chunk in the reduction loops
+
+// ------------------------------------------------------------ reductions ----
+// Wavefront reductions with DPP (within rows of 16 lanes) and readlane (across
+// the four rows).  Every lane must be active; the result is the same, bit for
+// bit, in every lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp64<0x141>(v);  // row_half_mirror
+    v += dpp64<0x140>(v);  // row_mirror
+    return v;
+}
+// lane l's value of v (readlane on the two 32-bit halves; the builtin's
+// return type is int, so a double must not be passed to it directly)
+__device__ __forceinline__ double rl64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double rows_total(double v) {
+    return (rl64(v, 0) + rl64(v, 16)) + (rl64(v, 32) + rl64(v, 48));
+}
+__device__ __forceinline__ double wave_sum(double v) { return rows_total(row_sum16(v)); }
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp64<0xB1>(v));
+    v = fmax(v, dpp64<0x4E>(v));
+    v = fmax(v, dpp64<0x141>(v));
+    v = fmax(v, dpp64<0x140>(v));
+    return fmax(fmax(rl64(v, 0), rl64(v, 16)), fmax(rl64(v, 32), rl64(v, 48)));
+}
+// 1/q to full precision: hardware reciprocal and two Newton steps
+__device__ __forceinline__ double recip(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(r, fma(-q, r, 1.0), r);
+    r = fma(r, fma(-q, r, 1.0), r);
+    return r;
+}
+
+// ---------------------------------------------------------- radial kernels ----
+template <int K>
+__device__ __forceinline__ double rbf_phi(double e2, double r2) {
+    double e = e2 * r2;
+    if (K == RBFFD_KERNEL_MQ) return sqrt(1.0 + e);
+    if (K == RBFFD_KERNEL_IMQ) return 1.0 / sqrt(1.0 + e);
+    return exp(-e);
+}
+// phi'(r)/r
+template <int K>
+__device__ __forceinline__ double rbf_psi(double e2, double r2) {
+    double e = e2 * r2;
+    if (K == RBFFD_KERNEL_MQ) return e2 / sqrt(1.0 + e);
+    if (K == RBFFD_KERNEL_IMQ) return -e2 / (sqrt(1.0 + e) * (1.0 + e));
+    return -2.0 * e2 * exp(-e);
+}
+
+// LDS of one stencil
+template <int NB>
+struct Shared {
+    static constexpr int MM = 64 * NB;
+    double x[MM], y[MM], z[MM];  // stencil node coordinates
+    double U[MM * RMAX];         // border basis values U[j*RMAX + k]
+    double T[RMAX * RMAX];       // monomial coefficients of the border basis T[l*RMAX + k]
+    double col[MM], vv[MM], ww[MM], vb[MM];
+    double pp[NB][MM];           // matvec partial sums per row block
+    double red[8];               // cross-wave partial sums
+    double d[MM], e[MM], e2[MM], tau[MM];
+    double fd[MM], fdu[MM], fdl[MM], ffact[MM];  // pivoted tridiagonal factors (fd: 1/pivot)
+    int fswap[MM];
+    double rhs[3][MM];
+    double zb[3][MM];
+    double hx[MM], hy[MM], hz[MM];
+    double nrm0[3];
+    int m, r, n, fact_ok;
+};
+
+// Position of a thread in the stencil's work group.
+struct Tid {
+    int lane;  // 0..63
+    int rb;    // row block (rows 64 rb + jj held in registers)
+    int cb;    // column block
+    int c;     // column index 64 cb + lane
+    int tid;   // 0 .. 64 NB^2 - 1 within the stencil's threads
+};
+
+template <int NB>
+__device__ __forceinline__ void bsync() {
+    if constexpr (NB == 1) {
+        // one wavefront: order LDS accesses and keep the compiler from moving them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Sum over the columns (lane-distributed; each column is held by NB threads).
+template <int NB>
+__device__ __forceinline__ double sum_cols(double v, Shared<NB>& S, const Tid& t) {
+    const double w = wave_sum(v);
+    if constexpr (NB == 1) {
+        return w;
+    } else {
+        if (t.rb == 0 && t.lane == 0) S.red[t.cb] = w;
+        bsync<NB>();
+        const double r = S.red[0] + S.red[1];
+        bsync<NB>();
+        return r;
+    }
+}
+template <int NB>
+__device__ __forceinline__ void sum_cols3(double& a, double& b, double& c, Shared<NB>& S, const Tid& t) {
+    a = rows_total(row_sum16(a));
+    b = rows_total(row_sum16(b));
+    c = rows_total(row_sum16(c));
+    if constexpr (NB == 2) {
+        if (t.rb == 0 && t.lane == 0) {
+            S.red[t.cb] = a;
+            S.red[2 + t.cb] = b;
+            S.red[4 + t.cb] = c;
+        }
+        bsync<NB>();
+        a = S.red[0] + S.red[1];
+        b = S.red[2] + S.red[3];
+        c = S.red[4] + S.red[5];
+        bsync<NB>();
+    }
+}
+// Sum over the rows held by lanes (row 64 rb + lane; cb == 0 waves count).
+template <int NB>
+__device__ __forceinline__ double sum_rows(double v, Shared<NB>& S, const Tid& t) {
+    const double w = wave_sum(v);
+    if constexpr (NB == 1) {
+        return w;
+    } else {
+        if (t.cb == 0 && t.lane == 0) S.red[6 + t.rb] = w;
+        bsync<NB>();
+        const double r = S.red[6] + S.red[7];
+        bsync<NB>();
+        return r;
+    }
+}
+template <int NB>
+__device__ __forceinline__ double max_cols(double v, Shared<NB>& S, const Tid& t) {
+    const double w = wave_max(v);
+    if constexpr (NB == 1) {
+        return w;
+    } else {
+        if (t.rb == 0 && t.lane == 0) S.red[t.cb] = w;
+        bsync<NB>();
+        const double r = fmax(S.red[0], S.red[1]);
+        bsync<NB>();
+        return r;
+    }
+}
+
+// ----------------------------------------------------------- local matrix ----
+// Column t.c, rows 64 rb .. 64 rb + 63 of A~(eps).
+template <int K, int NB>
+__device__ __forceinline__ void build_matrix(double (&a)[64], const Shared<NB>& S, const Tid& t, double e2) {
+    const int n = S.n, m = S.m, c = t.c;
+    const int cc = c < n ? c : 0;
+    const double xi = S.x[cc], yi = S.y[cc], zi = S.z[cc];
+    const int r0 = 64 * t.rb;
+#pragma unroll
+    for (int jj = 0; jj < 64; ++jj) {
+        const int j = r0 + jj;
+        double v = 0.0;
+        if (j < n) {
+            if (c < n) {
+                const double dx = xi - S.x[j], dy = yi - S.y[j], dz = zi - S.z[j];
+                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                v = rbf_phi<K>(e2, r2);
+            } else if (c < m) {
+                v = S.U[j * RMAX + (c - n)];
+            }
+        } else if (j < m) {
+            if (c < n) v = S.U[c * RMAX + (j - n)];
+        }
+        a[jj] = v;
+    }
+}
+
+// Householder tridiagonalisation of the m x m leading block (lane = column).
+// On return: S.d[0..m-1], S.e[0..m-2] (and e^2), S.tau[0..m-3], and row k of
+// the register matrix holds the reflector v_k (v_k[k+1] = 1).
+template <int NB>
+__device__ __forceinline__ void tridiagonalise(double (&a)[64], Shared<NB>& S, const Tid& t) {
+    const int m = S.m, c = t.c, r0 = 64 * t.rb;
+    if (t.rb == 0) S.col[c] = a[0];
+    bsync<NB>();
+    for (int k = 0; k < m - 2; ++k) {
+        const double xi = S.col[c];
+        const double alpha = S.col[k + 1];
+        const double dk = S.col[k];
+        const bool tail = c > k + 1 && c < m;
+        const double xnorm2 = sum_cols<NB>(tail ? xi * xi : 0.0, S, t);
+        double tau = 0.0, beta = alpha, scal = 0.0;
+        if (xnorm2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        const double vi = (c == k + 1) ? 1.0 : (tail ? xi * scal : 0.0);
+        if (t.tid == 0) {
+            S.d[k] = dk;
+            S.e[k] = beta;
+            S.e2[k] = beta * beta;
+            S.tau[k] = tau;
+        }
+        if (t.rb == 0) S.vv[c] = vi;
+        bsync<NB>();
+        // p = A v over this thread's rows (rows <= k hold zero weight in v)
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < 64; j0 += CH) {
+            if (r0 + j0 + CH > k + 1 && r0 + j0 < m) {
+#pragma unroll
+                for (int q = 0; q < CH; q += 2) {
+                    p0 = fma(a[j0 + q], S.vv[r0 + j0 + q], p0);
+                    p1 = fma(a[j0 + q + 1], S.vv[r0 + j0 + q + 1], p1);
+                }
+            }
+        }
+        double p = p0 + p1;
+        if constexpr (NB == 2) {
+            S.pp[t.rb][c] = p;
+            bsync<NB>();
+            p = S.pp[0][c] + S.pp[1][c];
+        }
+        double wi = (c > k && c < m) ? tau * p : 0.0;
+        const double s = sum_cols<NB>(wi * vi, S, t);
+        wi = fma(-0.5 * tau * s, vi, wi);
+        if (t.rb == 0) S.ww[c] = wi;
+        bsync<NB>();
+        // A -= v w^T + w v^T; store v in row k; publish row k+1 as the next pivot column
+#pragma unroll
+        for (int j0 = 0; j0 < 64; j0 += CH) {
+            if (r0 + j0 + CH > k + 1 && r0 + j0 < m) {
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+                    a[j0 + q] = fma(-S.vv[r0 + j0 + q], wi, fma(-S.ww[r0 + j0 + q], vi, a[j0 + q]));
+            }
+            if (r0 + j0 <= k + 1 && k < r0 + j0 + CH) {  // this chunk holds row k or row k + 1
+#pragma unroll
+                for (int q = 0; q < CH; ++q) {
+                    if (r0 + j0 + q == k) a[j0 + q] = vi;
+                    if (r0 + j0 + q == k + 1) S.col[c] = a[j0 + q];
+                }
+            }
+        }
+        bsync<NB>();
+    }
+    // trailing 2 x 2 block
+#pragma unroll
+    for (int jj = 0; jj < 64; ++jj)
+        if (r0 + jj == m - 1) S.ww[c] = a[jj];
+    bsync<NB>();
+    if (t.tid == 0) {
+        if (m >= 2) {
+            S.d[m - 2] = S.col[m - 2];
+            S.e[m - 2] = S.col[m - 1];
+            S.e2[m - 2] = S.col[m - 1] * S.col[m - 1];
+        }
+        S.d[m - 1] = S.ww[m - 1];
+    }
+    bsync<NB>();
+}
+
+// ------------------------------------------------------------ Sturm counts ----
+// Number of eigenvalues of T below sigma.  Wave-local: every wave of a
+// stencil may evaluate these (they read only S.d, S.e2).
+template <int NB>
+__device__ __forceinline__ int sturm(const Shared<NB>& S, int m, double sigma, double pivmin) {
+    double q = S.d[0] - sigma;
+    if (fabs(q) < pivmin) q = -pivmin;
+    int c = q < 0.0 ? 1 : 0;
+    for (int i = 1; i < m; ++i) {
+        q = fma(-S.e2[i - 1], recip(q), S.d[i] - sigma);
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += q < 0.0 ? 1 : 0;
+    }
+    return c;
+}
+
+struct Spectrum {
+    double amax;  // max |lambda|
+    bool finite;
+    double pivmin;
+};
+
+// Largest |lambda| of T to ~33^-rounds of the Gershgorin width.
+template <int NB>
+__device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, int rounds) {
+    const int m = S.m;
+    Spectrum sp;
+    double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
+    bool fin = true;
+    for (int i = 0; i < m; ++i) {
+        const double off = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i < m - 1 ? fabs(S.e[i]) : 0.0);
+        gl = fmin(gl, S.d[i] - off);
+        gu = fmax(gu, S.d[i] + off);
+        if (i < m - 1) emax2 = fmax(emax2, S.e2[i]);
+        fin = fin && isfinite(S.d[i]) && (i == m - 1 || isfinite(S.e[i]));
+    }
+    sp.finite = fin;
+    sp.pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    const double w = gu - gl;
+    gl -= 2.0 * w * 2.2e-16 + 2.0 * sp.pivmin;
+    gu += 2.0 * w * 2.2e-16 + 2.0 * sp.pivmin;
+    if (!fin) {
+        sp.amax = NAN;
+        return sp;
+    }
+    // lanes 0..31: smallest eigenvalue (index 1); lanes 32..63: largest (index m)
+    double lo1 = gl, hi1 = gu, lo2 = gl, hi2 = gu;
+    const int g = lane >> 5, tt = lane & 31;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const double lo = g ? lo2 : lo1, hi = g ? hi2 : hi1;
+        const double sig = lo + (hi - lo) * (double)(tt + 1) / 33.0;
+        const int kidx = g ? m : 1;
+        const bool below = sturm<NB>(S, m, sig, sp.pivmin) < kidx;  // eigenvalue kidx lies above sig
+        const uint64_t bal = __ballot(below);
+        const int nb1 = __popcll(bal & 0xffffffffull);
+        const int nb2 = __popcll(bal >> 32);
+        const double n_lo1 = nb1 > 0 ? lo1 + (hi1 - lo1) * (double)nb1 / 33.0 : lo1;
+        const double n_hi1 = nb1 < 32 ? lo1 + (hi1 - lo1) * (double)(nb1 + 1) / 33.0 : hi1;
+        const double n_lo2 = nb2 > 0 ? lo2 + (hi2 - lo2) * (double)nb2 / 33.0 : lo2;
+        const double n_hi2 = nb2 < 32 ? lo2 + (hi2 - lo2) * (double)(nb2 + 1) / 33.0 : hi2;
+        lo1 = n_lo1; hi1 = n_hi1; lo2 = n_lo2; hi2 = n_hi2;
+    }
+    sp.amax = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
+    return sp;
+}
+
+// #eigenvalues with |lambda| < tau for two thresholds (lanes 0-1 and 2-3)
+template <int NB>
+__device__ __forceinline__ void small_counts(const Shared<NB>& S, int lane, const Spectrum& sp, double tau_a,
+                                             double tau_b, int& ca, int& cb) {
+    const int m = S.m;
+    double sig = 0.0;
+    if (lane == 0) sig = -tau_a;
+    if (lane == 1) sig = tau_a;
+    if (lane == 2) sig = -tau_b;
+    if (lane == 3) sig = tau_b;
+    const int c = lane < 4 ? sturm<NB>(S, m, sig, sp.pivmin) : 0;
+    const int c0 = __shfl(c, 0, 64), c1 = __shfl(c, 1, 64), c2 = __shfl(c, 2, 64), c3 = __shfl(c, 3, 64);
+    ca = c1 - c0;
+    cb = c3 - c2;
+}
+
+// Smallest |lambda| (geometric multisection on both sides of zero).
+template <int NB>
+__device__ __forceinline__ double spectrum_min_abs(const Shared<NB>& S, int lane, const Spectrum& sp, int rounds) {
+    const int m = S.m;
+    const int nu = sturm<NB>(S, m, 0.0, sp.pivmin);  // eigenvalues below zero (uniform)
+    const double H = sp.amax * (1.0 + 1e-12) + sp.pivmin;
+    const double L = sp.amax * 1e-30 + sp.pivmin;
+    double lp = log(L), hp = log(H), ln_ = log(L), hn = log(H);
+    const int g = lane >> 5, tt = lane & 31;
+    for (int rd = 0; rd < rounds; ++rd) {
+        const double lo = g ? ln_ : lp, hi = g ? hn : hp;
+        const double sig = exp(lo + (hi - lo) * (double)(tt + 1) / 33.0);
+        bool above;  // target magnitude lies above sig
+        if (g == 0) above = sturm<NB>(S, m, sig, sp.pivmin) <= nu;   // lambda_{nu+1} > sig
+        else above = sturm<NB>(S, m, -sig, sp.pivmin) >= nu;         // lambda_nu < -sig
+        const uint64_t bal = __ballot(above);
+        const int nb1 = __popcll(bal & 0xffffffffull);
+        const int nb2 = __popcll(bal >> 32);
+        const double a1 = lp + (hp - lp) * (double)nb1 / 33.0, b1 = lp + (hp - lp) * (double)(nb1 + 1) / 33.0;
+        const double a2 = ln_ + (hn - ln_) * (double)nb2 / 33.0, b2 = ln_ + (hn - ln_) * (double)(nb2 + 1) / 33.0;
+        if (nb1 > 0) lp = a1;
+        if (nb1 < 32) hp = b1;
+        if (nb2 > 0) ln_ = a2;
+        if (nb2 < 32) hn = b2;
+    }
+    const double pos = nu < m ? exp(0.5 * (lp + hp)) : INFINITY;
+    const double neg = nu > 0 ? exp(0.5 * (ln_ + hn)) : INFINITY;
+    return fmin(pos, neg);
+}
+
+// ------------------------------------------------------- tridiagonal solve ----
+// Gaussian elimination with partial pivoting of T (one thread); false on a zero pivot.
+template <int NB>
+__device__ __forceinline__ bool tri_factor(Shared<NB>& S) {
+    const int m = S.m;
+    for (int i = 0; i < m; ++i) {
+        S.fd[i] = S.d[i];
+        S.fdu[i] = i < m - 1 ? S.e[i] : 0.0;
+        S.fdl[i] = i < m - 1 ? S.e[i] : 0.0;  // sub-diagonal, later the second super-diagonal
+    }
+    for (int i = 0; i < m - 1; ++i) {
+        const double sub = S.fdl[i];
+        if (fabs(S.fd[i]) >= fabs(sub)) {
+            if (S.fd[i] == 0.0) return false;
+            const double f = sub / S.fd[i];
+            S.fd[i + 1] -= f * S.fdu[i];
+            S.fdl[i] = 0.0;
+            S.ffact[i] = f;
+            S.fswap[i] = 0;
+        } else {
+            const double f = S.fd[i] / sub;
+            S.fd[i] = sub;
+            const double tmp = S.fd[i + 1];
+            S.fd[i + 1] = S.fdu[i] - f * tmp;
+            if (i < m - 2) {
+                S.fdl[i] = S.fdu[i + 1];
+                S.fdu[i + 1] = -f * S.fdl[i];
+            } else {
+                S.fdl[i] = 0.0;
+            }
+            S.fdu[i] = tmp;
+            S.ffact[i] = f;
+            S.fswap[i] = 1;
+        }
+    }
+    if (S.fd[m - 1] == 0.0) return false;
+    for (int i = 0; i < m; ++i) S.fd[i] = 1.0 / S.fd[i];  // keep reciprocals of the pivots
+    return true;
+}
+
+template <int NB>
+__device__ __forceinline__ void tri_solve(const Shared<NB>& S, double* b) {
+    const int m = S.m;
+    for (int i = 0; i < m - 1; ++i) {
+        const double f = S.ffact[i];
+        if (!S.fswap[i]) {
+            b[i + 1] -= f * b[i];
+        } else {
+            const double tt = b[i];
+            b[i] = b[i + 1];
+            b[i + 1] = tt - f * b[i + 1];
+        }
+    }
+    b[m - 1] *= S.fd[m - 1];
+    if (m > 1) b[m - 2] = (b[m - 2] - S.fdu[m - 2] * b[m - 1]) * S.fd[m - 2];
+    for (int i = m - 3; i >= 0; --i) b[i] = (b[i] - S.fdu[i] * b[i + 1] - S.fdl[i] * b[i + 2]) * S.fd[i];
+}
+
+// y <- Q^T y (FWD) or y <- Q y, for NV = 1 or 3 vectors (thread holds component
+// t.c).  The reflector v_k is register row k (NB = 1) or is published through
+// LDS by the row block that holds row k (NB = 2).
+template <int NB, int NV, bool FWD>
+__device__ __forceinline__ void apply_q(const double (&a)[64], Shared<NB>& S, const Tid& t, double (&y)[3]) {
+    const int m = S.m;
+    constexpr int MM = 64 * NB;
+#pragma unroll
+    for (int kk = 0; kk < MM - 2; ++kk) {
+        const int k = FWD ? kk : MM - 3 - kk;  // a compile-time constant after unrolling
+        if (k < m - 2) {
+            double v;
+            if constexpr (NB == 1) {
+                v = a[k];
+            } else {
+                if (t.rb == k / 64) S.vb[t.c] = a[k % 64];
+                bsync<NB>();
+                v = S.vb[t.c];
+            }
+            if constexpr (NV == 3) {
+                double s0 = v * y[0], s1 = v * y[1], s2 = v * y[2];
+                sum_cols3<NB>(s0, s1, s2, S, t);  // ends with a barrier when NB = 2
+                const double ta = S.tau[k];
+                y[0] = fma(-ta * s0, v, y[0]);
+                y[1] = fma(-ta * s1, v, y[1]);
+                y[2] = fma(-ta * s2, v, y[2]);
+            } else {
+                const double s0 = sum_cols<NB>(v * y[0], S, t);
+                y[0] = fma(-S.tau[k] * s0, v, y[0]);
+            }
+        }
+    }
+}
+
+// y <- A~^{-1} y via Q T^{-1} Q^T
+template <int NB, int NV>
+__device__ __forceinline__ void solve(const double (&a)[64], Shared<NB>& S, const Tid& t, double (&y)[3]) {
+    const int m = S.m;
+    apply_q<NB, NV, true>(a, S, t, y);
+    if (t.rb == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.rhs[v][t.c] = y[v];
+    }
+    bsync<NB>();
+    if (t.tid < NV) tri_solve<NB>(S, S.rhs[t.tid]);
+    bsync<NB>();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) y[v] = t.c < m ? S.rhs[v][t.c] : 0.0;
+    bsync<NB>();
+    apply_q<NB, NV, false>(a, S, t, y);
+}
+
+// (A~ z) row t.c for NV vectors read from S.zb; A~ re-evaluated from the nodes
+template <int K, int NB, int NV>
+__device__ __forceinline__ void matvec_lds(const Shared<NB>& S, const Tid& t, double e2, double (&out)[3]) {
+    const int n = S.n, m = S.m, r = S.r, c = t.c;
+    out[0] = out[1] = out[2] = 0.0;
+    if (c < n) {
+        const double xi = S.x[c], yi = S.y[c], zi = S.z[c];
+        for (int j = 0; j < n; ++j) {
+            const double dx = xi - S.x[j], dy = yi - S.y[j], dz = zi - S.z[j];
+            const double av = rbf_phi<K>(e2, (dx * dx + dy * dy) + dz * dz);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v] = fma(av, S.zb[v][j], out[v]);
+        }
+        for (int k = 0; k < r; ++k) {
+            const double u = S.U[c * RMAX + k];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v] = fma(u, S.zb[v][n + k], out[v]);
+        }
+    } else if (c < m) {
+        const int k = c - n;
+        for (int j = 0; j < n; ++j) {
+            const double u = S.U[j * RMAX + k];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) out[v] = fma(u, S.zb[v][j], out[v]);
+        }
+    }
+}
+
+// Solve with one step of iterative refinement: z = A~^{-1} b, z += A~^{-1}(b - A~ z).
+// The Householder route alone leaves an error several times that of LU with
+// partial pivoting on these ill-conditioned saddle systems; one step brings it
+// to that level.
+template <int K, int NB, int NV>
+__device__ __forceinline__ void solve_refined(const double (&a)[64], Shared<NB>& S, const Tid& t, double e2,
+                                              double (&y)[3]) {
+    const double b[3] = {y[0], y[1], y[2]};
+    solve<NB, NV>(a, S, t, y);
+    if (t.rb == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.zb[v][t.c] = y[v];
+    }
+    bsync<NB>();
+    double az[3];
+    matvec_lds<K, NB, NV>(S, t, e2, az);
+    bsync<NB>();
+    double r[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r[v] = t.c < S.m ? b[v] - az[v] : 0.0;
+    solve<NB, NV>(a, S, t, r);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) y[v] += r[v];
+}
+
+// --------------------------------------------------------------- border ----
+// Monomials in xi (order: 1, x, y, z, x^2, y^2, z^2, xy, xz, yz) at row
+// jr = 64 rb + lane, orthonormalised by MGS with one reorthogonalisation; kept
+// columns go to S.U and their monomial coefficients to S.T.  Degree 0 is the
+// plain column of ones.
+template <int NB>
+__device__ __forceinline__ void build_border(Shared<NB>& S, const Tid& t, int degree, double rank_tol, double xr, double yr,
+                             double zr) {
+    const int n = S.n;
+    const int jr = 64 * t.rb + t.lane;
+    if (degree == 0) {
+        if (t.cb == 0 && jr < n) S.U[jr * RMAX] = 1.0;
+        if (t.tid < RMAX) S.T[t.tid * RMAX] = t.tid == 0 ? 1.0 : 0.0;
+        if (t.tid == 0) S.r = 1;
+        bsync<NB>();
+        return;
+    }
+    const int M = degree == 1 ? 4 : 10;
+    const bool act = jr < n;
+    double u[RMAX];
+    u[0] = 1.0; u[1] = xr; u[2] = yr; u[3] = zr;
+    u[4] = xr * xr; u[5] = yr * yr; u[6] = zr * zr; u[7] = xr * yr; u[8] = xr * zr; u[9] = yr * zr;
+#pragma unroll
+    for (int l = 0; l < RMAX; ++l)
+        if (!act) u[l] = 0.0;
+    // thread l (< M) of the stencil holds row l of the coefficient matrix
+    double tc[RMAX];
+#pragma unroll
+    for (int q = 0; q < RMAX; ++q) tc[q] = (t.tid == q) ? 1.0 : 0.0;
+    bool keep[RMAX];
+    int r = 0;
+#pragma unroll
+    for (int l = 0; l < RMAX; ++l) {
+        keep[l] = false;
+        if (l < M) {
+            const double on2 = sum_rows<NB>(u[l] * u[l], S, t);
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+#pragma unroll
+                for (int q = 0; q < RMAX; ++q) {  // constant trip count: u, tc, keep stay in registers
+                    if (q < l && keep[q]) {
+                        const double cq = sum_rows<NB>(u[q] * u[l], S, t);
+                        u[l] = fma(-cq, u[q], u[l]);
+                        tc[l] = fma(-cq, tc[q], tc[l]);
+                    }
+                }
+            }
+            const double n2 = sum_rows<NB>(u[l] * u[l], S, t);
+            if (n2 > rank_tol * rank_tol * on2 && n2 > 0.0) {
+                const double inv = 1.0 / sqrt(n2);
+                u[l] *= inv;
+                tc[l] *= inv;
+                keep[l] = true;
+                if (act && t.cb == 0) S.U[jr * RMAX + r] = u[l];
+                if (t.tid < RMAX) S.T[t.tid * RMAX + r] = tc[l];
+                ++r;
+            }
+        }
+    }
+    if (t.tid == 0) S.r = r;
+    bsync<NB>();
+}
+
+// ------------------------------------------------------ kappa evaluations ----
+template <int K, int NB>
+__device__ __forceinline__ Spectrum eval_spectrum(double (&a)[64], Shared<NB>& S, const Tid& t, double eps,
+                                                  int rounds) {
+    build_matrix<K, NB>(a, S, t, eps * eps);
+    tridiagonalise<NB>(a, S, t);
+    return spectrum_max<NB>(S, t.lane, rounds);
+}
+
+// kappa > target ?  (non-finite counts as above, like an infinite kappa)
+template <int NB>
+__device__ __forceinline__ bool kappa_above(const Shared<NB>& S, int lane, const Spectrum& sp, double target) {
+    if (!sp.finite || !(sp.amax > 0.0)) return true;
+    int ca, cb;
+    small_counts<NB>(S, lane, sp, sp.amax / target, sp.amax / target, ca, cb);
+    return ca > 0;
+}
+
+// --------------------------------------------------------------- stencil ----
+// The whole computation for stencil s of job J by the NB^2 waves of one stencil.
+template <int K, int NB>
+__device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<NB>& S, const Tid& t) {
+    const WOpts& o = J.o;
+    const int n = o.n;
+    const int c = t.c;
+    // ---- gather the stencil (thread's column node; rb == 0 threads fill LDS)
+    double px = 0, py = 0, pz = 0, nx = 0, ny = 0, nz = 0;
+    if (c < n) {
+        const int64_t node = J.idx[s * n + c];
+        px = J.xyz[3 * node];
+        py = J.xyz[3 * node + 1];
+        pz = J.xyz[3 * node + 2];
+        if (J.nrm) {
+            nx = J.nrm[3 * node];
+            ny = J.nrm[3 * node + 1];
+            nz = J.nrm[3 * node + 2];
+            const double nn = sqrt(nx * nx + ny * ny + nz * nz);
+            nx /= nn; ny /= nn; nz /= nn;
+        }
+        if (t.rb == 0) {
+            S.x[c] = px;
+            S.y[c] = py;
+            S.z[c] = pz;
+        }
+    }
+    if (t.tid == 0) {
+        S.nrm0[0] = nx; S.nrm0[1] = ny; S.nrm0[2] = nz;
+        S.n = n;
+    }
+    bsync<NB>();
+    // ---- stencil radius, scaled offsets of the thread's column node and row node
+    const double dx0 = px - S.x[0], dy0 = py - S.y[0], dz0 = pz - S.z[0];
+    const double r20 = c < n ? (dx0 * dx0 + dy0 * dy0) + dz0 * dz0 : 0.0;
+    const double dupf = max_cols<NB>((c > 0 && c < n && r20 == 0.0) ? 1.0 : 0.0, S, t);
+    const double rho = sqrt(max_cols<NB>(r20, S, t));
+    const double irho = 1.0 / rho;
+    const double xi = dx0 / rho, yi = dy0 / rho, zi = dz0 / rho;
+    const int jr = 64 * t.rb + t.lane;
+    double xr = 0, yr = 0, zr = 0;
+    if (jr < n) {
+        xr = (S.x[jr] - S.x[0]) / rho;
+        yr = (S.y[jr] - S.y[0]) / rho;
+        zr = (S.z[jr] - S.z[0]) / rho;
+    }
+    build_border<NB>(S, t, o.degree, o.rank_tol, xr, yr, zr);
+    if (t.tid == 0) S.m = n + S.r;
+    bsync<NB>();
+    int status = RBFFD_ST_OK;
+    int evals = 0;
+    double a[64];
+    double eps;
+    if (dupf > 0.0) status = RBFFD_ST_DUPLICATE;
+
+    // ---- shape parameter
+    bool have_final = false;  // registers / S hold the tridiagonal form at eps
+    Spectrum sp;
+    if (o.mode == RBFFD_EPS_FIXED) {
+        eps = o.eps_fixed;
+    } else if (o.mode == RBFFD_EPS_GIVEN) {
+        eps = J.eps_in[s];
+    } else {
+        bool need_bisect = true;
+        if (o.mode == RBFFD_EPS_LEARNED) {
+            eps = J.eps_in[s];
+            if (isfinite(eps) && eps > 0.0) {
+                sp = eval_spectrum<K, NB>(a, S, t, eps, 8);  // also the reported kappa if kept
+                ++evals;
+                if (sp.finite && sp.amax > 0.0) {
+                    int c_lo, c_hi;  // |lambda| below amax/band_lo and below amax/band_hi
+                    small_counts<NB>(S, t.lane, sp, sp.amax / o.band_lo, sp.amax / o.band_hi, c_lo, c_hi);
+                    if (c_lo > 0 && c_hi == 0) {  // band_lo < kappa <= band_hi
+                        need_bisect = false;
+                        have_final = true;
+                    }
+                }
+            }
+            if (need_bisect && status == RBFFD_ST_OK) status = RBFFD_ST_FALLBACK;
+        }
+        if (need_bisect) {
+            double lo = o.br_lo / rho, hi = o.br_hi / rho;
+            sp = eval_spectrum<K, NB>(a, S, t, lo, 2);
+            ++evals;
+            bool ab = kappa_above<NB>(S, t.lane, sp, o.kappa_target);
+            for (int q = 0; !ab && q < o.max_expand; ++q) {
+                lo *= 0.5;
+                sp = eval_spectrum<K, NB>(a, S, t, lo, 2);
+                ++evals;
+                ab = kappa_above<NB>(S, t.lane, sp, o.kappa_target);
+            }
+            bool ok = ab;
+            sp = eval_spectrum<K, NB>(a, S, t, hi, 2);
+            ++evals;
+            ab = kappa_above<NB>(S, t.lane, sp, o.kappa_target);
+            for (int q = 0; ab && q < o.max_expand; ++q) {
+                hi *= 2.0;
+                sp = eval_spectrum<K, NB>(a, S, t, hi, 2);
+                ++evals;
+                ab = kappa_above<NB>(S, t.lane, sp, o.kappa_target);
+            }
+            ok = ok && !ab;
+            if (!ok && status == RBFFD_ST_OK) status = RBFFD_ST_NO_BRACKET;
+            bool stop = false;
+            while (hi - lo > o.eps_tol && !stop) {
+                const double mid = 0.5 * (lo + hi);
+                sp = eval_spectrum<K, NB>(a, S, t, mid, 2);
+                ++evals;
+                if (o.band_stop && sp.finite && sp.amax > 0.0) {
+                    int c_lo, c_hi;
+                    small_counts<NB>(S, t.lane, sp, sp.amax / o.band_lo, sp.amax / o.band_hi, c_lo, c_hi);
+                    if (c_lo > 0 && c_hi == 0) {
+                        eps = mid;
+                        stop = true;
+                        have_final = true;
+                        sp = spectrum_max<NB>(S, t.lane, 8);  // full precision for the reported kappa
+                        break;
+                    }
+                }
+                if (kappa_above<NB>(S, t.lane, sp, o.kappa_target)) lo = mid;
+                else hi = mid;
+            }
+            if (!stop) eps = 0.5 * (lo + hi);
+        }
+    }
+    if (!have_final) {
+        sp = eval_spectrum<K, NB>(a, S, t, eps, 8);
+        ++evals;
+    }
+    // ---- kappa_2 at the final eps
+    double kappa = NAN;
+    if (sp.finite && sp.amax > 0.0) {
+        const double amin = spectrum_min_abs<NB>(S, t.lane, sp, 7);
+        kappa = sp.amax / amin;
+    } else if (status == RBFFD_ST_OK) {
+        status = RBFFD_ST_NONFINITE;
+    }
+    if (!sp.finite && status == RBFFD_ST_OK) status = RBFFD_ST_NONFINITE;
+    if (t.tid == 0) {
+        if (J.eps) J.eps[s] = eps;
+        if (J.kappa) J.kappa[s] = kappa;
+        if (J.nevals) J.nevals[s] = evals;
+    }
+    if (J.kappa_only) {
+        if (t.tid == 0 && J.status) J.status[s] = status;
+        bsync<NB>();
+        return;
+    }
+
+    // ---- weights: w = (A~^{-1} r)[:n], r = sum_d (B^d)^T g_d, g_d = (A~^{-1} b_d)[:n]
+    if (t.tid == 0) S.fact_ok = sp.finite ? (int)tri_factor<NB>(S) : 0;
+    bsync<NB>();
+    const int m = S.m;
+    if (!S.fact_ok) {
+        if (status == RBFFD_ST_OK) status = sp.finite ? RBFFD_ST_SINGULAR : RBFFD_ST_NONFINITE;
+        if (t.tid == 0 && J.status) J.status[s] = status;
+        if (c < n && t.rb == 0) J.w[s * n + c] = NAN;
+        bsync<NB>();
+        return;
+    }
+    const double e2 = eps * eps;
+    const double n0x = S.nrm0[0], n0y = S.nrm0[1], n0z = S.nrm0[2];
+    // b_d (row 1 of B^d) as an m-vector, component c
+    double b[3] = {0.0, 0.0, 0.0};
+    if (c < n) {
+        const double dx = S.x[0] - px, dy = S.y[0] - py, dz = S.z[0] - pz;  // x_1 - x_j
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        const double ps = rbf_psi<K>(e2, r2);
+        const double dn = n0x * dx + n0y * dy + n0z * dz;
+        b[0] = ps * (dx - n0x * dn);
+        b[1] = ps * (dy - n0y * dn);
+        b[2] = ps * (dz - n0z * dn);
+    } else if (c < m && o.degree > 0) {
+        const int k = c - n;  // grad q_k at the centre (xi = 0): linear coefficients / rho
+        const double gx = S.T[1 * RMAX + k] * irho, gy = S.T[2 * RMAX + k] * irho, gz = S.T[3 * RMAX + k] * irho;
+        const double dn = n0x * gx + n0y * gy + n0z * gz;
+        b[0] = gx - n0x * dn;
+        b[1] = gy - n0y * dn;
+        b[2] = gz - n0z * dn;
+    }
+    solve_refined<K, NB, 3>(a, S, t, e2, b);
+    // h_i = Pi_i g_i
+    double hx = 0, hy = 0, hz = 0;
+    if (c < n) {
+        const double dn = nx * b[0] + ny * b[1] + nz * b[2];
+        hx = b[0] - nx * dn;
+        hy = b[1] - ny * dn;
+        hz = b[2] - nz * dn;
+    }
+    if (t.rb == 0) {
+        S.hx[c] = hx;
+        S.hy[c] = hy;
+        S.hz[c] = hz;
+    }
+    bsync<NB>();
+    // r_j = sum_i psi(r_ij) (x_i - x_j) . h_i   (j = c < n)
+    double rj = 0.0;
+    if (c < n) {
+#pragma unroll 4
+        for (int i = 0; i < n; ++i) {
+            const double dx = S.x[i] - px, dy = S.y[i] - py, dz = S.z[i] - pz;
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            const double ps = rbf_psi<K>(e2, r2);
+            rj = fma(ps, dx * S.hx[i] + dy * S.hy[i] + dz * S.hz[i], rj);
+        }
+    }
+    // r_{n+k} = sum_i grad q_k(x_i) . h_i
+    if (o.degree > 0) {
+        const int r = S.r;
+        for (int k = 0; k < r; ++k) {
+            double cv = 0.0;
+            if (c < n) {
+                const double* T = S.T;
+                double gx = T[1 * RMAX + k], gy = T[2 * RMAX + k], gz = T[3 * RMAX + k];
+                if (o.degree == 2) {
+                    const double t4 = T[4 * RMAX + k], t5 = T[5 * RMAX + k], t6 = T[6 * RMAX + k];
+                    const double t7 = T[7 * RMAX + k], t8 = T[8 * RMAX + k], t9 = T[9 * RMAX + k];
+                    gx += 2.0 * t4 * xi + t7 * yi + t8 * zi;
+                    gy += 2.0 * t5 * yi + t7 * xi + t9 * zi;
+                    gz += 2.0 * t6 * zi + t8 * xi + t9 * yi;
+                }
+                cv = (gx * hx + gy * hy + gz * hz) * irho;
+            }
+            cv = sum_cols<NB>(cv, S, t);
+            if (c == n + k) rj = cv;
+        }
+    }
+    double wv[3] = {rj, 0.0, 0.0};
+    solve_refined<K, NB, 1>(a, S, t, e2, wv);
+    if (c < n && t.rb == 0) J.w[s * n + c] = wv[0];
+    if (t.tid == 0 && J.status) J.status[s] = status;
+    bsync<NB>();
+}
+
+}  // namespace rbw

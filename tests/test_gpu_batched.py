@@ -1,0 +1,165 @@
+"""Batched weights over many surfaces (persistent launches, autotuned
+schedule) and the block-diagonal operator of many surfaces.
+
+The batched build runs the same per-stencil routine as the plain build, so
+its outputs are compared bit for bit with per-surface rbffd_build_weights;
+the plain build is itself held to the oracle in test_gpu_parity.py, and a
+sample of the batch is checked against the oracle here too.  The batched
+operator is compared with the per-surface operators (bit for bit: the same
+sums in the same order) and, for one surface, with the oracle.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.shape import bisect_eps
+from oracle.stepper import laplacian_apply
+from oracle.weights import build_weights as oracle_weights
+from synth import surface_batch
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    """Nine surfaces: spheres, tori, ellipsoids; n in {31, 50, 70, 101}; N ragged."""
+    surfs = surface_batch(count=9, seed=17, n_min=400, n_max=2500)
+    return [(dev(s["X"]), dev(s["nrm"]), s["n"]) for s in surfs], surfs
+
+
+def _same(a, b):
+    return torch.equal(a, b) or (torch.isnan(a).equal(torch.isnan(b)) and
+                                 torch.equal(torch.nan_to_num(a, nan=0.0), torch.nan_to_num(b, nan=0.0)))
+
+
+@pytest.mark.parametrize("tuning", [None, "odd"])
+def test_batched_matches_plain_bitwise(lib, batch, tuning):
+    surfs, meta = batch
+    print(f"[batched] {len(surfs)} surfaces n={[s[2] for s in surfs]} N={[s[0].shape[0] for s in surfs]} "
+          f"tuning={tuning}", flush=True)
+    tun = None
+    if tuning == "odd":  # item sizes that leave ragged tails, one group per CU, given order
+        tun = [dict(stencils_per_item=7, groups_per_cu=1, order=1), dict(stencils_per_item=3, groups_per_cu=1, order=1)]
+    got = lib.build_weights_batched(surfs, tuning=tun, eps_mode="bisect", kappa_target=1e12)
+    for (X, nrm, n), g in zip(surfs, got):
+        ref = lib.build_weights(X, nrm, n, eps_mode="bisect", kappa_target=1e12)
+        torch.cuda.synchronize()
+        assert torch.equal(g.idx, ref.idx)
+        assert _same(g.w, ref.w)
+        assert torch.equal(g.eps, ref.eps)
+        assert _same(g.kappa, ref.kappa)
+        assert torch.equal(g.status, ref.status)
+        assert torch.equal(g.nevals, ref.nevals)
+
+
+def test_batched_sample_against_oracle(lib, batch):
+    surfs, meta = batch
+    got = lib.build_weights_batched(surfs, eps_mode="bisect", kappa_target=1e12)
+    rng = np.random.default_rng(5)
+    for s in (0, 4, 8):
+        X, nrm, n = meta[s]["X"], meta[s]["nrm"], meta[s]["n"]
+        idx = host(got[s].idx)
+        eg = host(got[s].eps)
+        for i in rng.choice(len(X), 4, replace=False):
+            eo, _, _, sto = bisect_eps(X[idx[i]], 1e12)
+            assert sto == 0 and abs(eg[i] - eo) <= 2e-4, (s, i, eg[i], eo)
+        rows = rng.choice(len(X), 4, replace=False)
+        wo = oracle_weights(X, nrm, idx, eg, rows=rows)
+        wg = host(got[s].w)[rows]
+        k = host(got[s].kappa)[rows]
+        err = np.linalg.norm(wg - wo, axis=1) / np.linalg.norm(wo, axis=1)
+        assert np.all(err <= np.maximum(1e-9, 0.5 * k * 2.0 ** -53)), err
+
+
+def test_autotune_and_cache(lib, batch, tmp_path):
+    surfs, _ = batch
+    path = str(tmp_path / "tune.json")
+    t1 = lib.autotune_batched(surfs, cache_path=path, retune=True, eps_mode="bisect", kappa_target=1e12)
+    assert len(t1) == 2
+    for t in t1:
+        assert t["stencils_per_item"] >= 1 and t["groups_per_cu"] in (1, 2) and t["order"] in (0, 1)
+        assert t["us_per_stencil"] > 0
+    data = json.load(open(path))
+    assert len(data) == 2 and all("bucket" in k for k in data)
+    # cached: same schedule without timing again
+    t2 = lib.autotune_batched(surfs, cache_path=path, eps_mode="bisect", kappa_target=1e12)
+    assert [(t["stencils_per_item"], t["groups_per_cu"], t["order"]) for t in t1] == \
+           [(t["stencils_per_item"], t["groups_per_cu"], t["order"]) for t in t2]
+    got = lib.build_weights_batched(surfs, tuning=t2, eps_mode="bisect", kappa_target=1e12)
+    ref = lib.build_weights_batched(surfs, eps_mode="bisect", kappa_target=1e12)
+    for g, r in zip(got, ref):
+        assert _same(g.w, r.w)
+
+
+def test_batched_errors(lib, batch):
+    surfs, _ = batch
+    X, nrm, _ = surfs[0]
+    with pytest.raises(lib.RbffdError, match="surface 1"):
+        lib.build_weights_batched([surfs[0], (X, nrm, 125)], eps_mode="fixed", eps=2.0)
+    with pytest.raises(lib.RbffdError):
+        lib.build_weights_batched(surfs[:2], tuning=[dict(stencils_per_item=0, groups_per_cu=1, order=0)] * 2)
+    assert lib.build_weights_batched([], eps_mode="fixed") == []
+
+
+@pytest.fixture(scope="module")
+def batch_ops(lib, batch):
+    surfs, meta = batch
+    res = lib.build_weights_batched(surfs[:4], eps_mode="bisect", kappa_target=1e10)
+    parts = []
+    for (X, nrm, n), r in zip(surfs[:4], res):
+        _, perm = lib.knn(X, n)
+        parts.append((r.idx, r.w, perm))
+    return parts, meta[:4]
+
+
+def test_batched_operator_apply_matches_per_surface(lib, batch_ops):
+    parts, meta = batch_ops
+    bop = lib.Operator.batched(parts)
+    Ns = [p[0].shape[0] for p in parts]
+    rng = np.random.default_rng(2)
+    u = [rng.standard_normal(N) for N in Ns]
+    ucat = dev(np.concatenate(u))
+    for prec in ("f64", "f32"):
+        got = host(bop.apply(ucat, prec=prec))
+        off = 0
+        for (idx, w, perm), us, N in zip(parts, u, Ns):
+            ref = host(lib.Operator(idx, w, perm).apply(dev(us), prec=prec))
+            assert np.array_equal(got[off:off + N], ref), prec
+            off += N
+    # one surface against the oracle's CSR operator (FP64)
+    idx, w, _ = parts[1]
+    ref = laplacian_apply(host(idx), host(w), u[1])
+    g = host(bop.apply(ucat, prec="f64"))[Ns[0]:Ns[0] + Ns[1]]
+    assert np.max(np.abs(g - ref)) <= 1e-13 * np.max(np.abs(host(w)).sum(axis=1) * np.max(np.abs(u[1])))
+
+
+def test_batched_operator_step_matches_per_surface(lib, batch_ops):
+    parts, _ = batch_ops
+    bop = lib.Operator.batched(parts)
+    Ns = [p[0].shape[0] for p in parts]
+    rng = np.random.default_rng(3)
+    u0 = [rng.standard_normal((2, N)) for N in Ns]
+    state = dev(np.concatenate(u0, axis=1))
+    params = (0.1, 0.9, 50.0)
+    for prec in ("f64", "f32"):
+        got = host(bop.step(state, 1e-6, 23, prec=prec, D=(1.0, 10.0), reaction="schnakenberg", params=params,
+                            graph_steps=5))
+        assert np.all(np.isfinite(got))
+        off = 0
+        for (idx, w, perm), us, N in zip(parts, u0, Ns):
+            ref = host(lib.Operator(idx, w, perm).step(dev(us), 1e-6, 23, prec=prec, D=(1.0, 10.0),
+                                                       reaction="schnakenberg", params=params, graph_steps=5))
+            assert np.array_equal(got[:, off:off + N], ref), prec
+            off += N

@@ -174,6 +174,35 @@ def test_bisection_parity_torus(lib):
     assert np.all(err <= tol), (err / tol).max()
 
 
+@pytest.mark.parametrize("n,kernel,degree", [(70, "mq", 2), (101, "mq", 2), (118, "mq", 2), (101, "imq", 0),
+                                             (70, "ga", 1)])
+def test_large_stencils_four_waves(lib, n, kernel, degree):
+    """m = n + border in (64, 128]: four wavefronts per stencil (n = 118 with
+    the degree-2 border is the largest system, m = 128).  Bisection to
+    kappa_T = 1e10 against the oracle's, then weights at the GPU's eps."""
+    X, nrm = fibonacci_sphere(2117)
+    idx = oracle_knn(X, n)
+    kT = 1e10
+    print(f"[weights4] sphere N=2117 n={n} {kernel} degree={degree} bisect kT={kT:g}", flush=True)
+    res = lib.build_weights(dev(X), dev(nrm), n, idx=dev(idx, torch.int32), eps_mode="bisect", kappa_target=kT,
+                            kernel=kernel, degree=degree)
+    eg, kg, st, ne, wg = host(res.eps), host(res.kappa), host(res.status), host(res.nevals), host(res.w)
+    rows = np.random.default_rng(n).choice(len(X), 24, replace=False)
+    rows[0] = len(X) - 1
+    for i in rows:
+        eo, ko, evo, sto = bisect_eps(X[idx[i]], kT, kernel=kernel, degree=degree)
+        assert st[i] == sto == 0, (i, st[i], sto)
+        assert abs(eg[i] - eo) <= 2e-4, (i, eg[i], eo)
+        assert abs(ne[i] - evo) <= 2
+    wo = oracle_weights(X, nrm, idx, eg, kernel=kernel, degree=degree, rows=rows)
+    kap = oracle_kappas(X, idx, eg, rows, kernel=kernel, degree=degree)
+    err, tol = weight_rule(wg[rows], wo, kap)
+    assert np.all(err <= tol), (err / tol).max()
+    assert np.all(np.abs(kg[rows] / kap - 1.0) <= 20 * kap * U64 + 1e-12), np.abs(kg[rows] / kap - 1).max()
+    # zero row sums (constants are reproduced) over every stencil
+    assert np.all(np.abs(wg.sum(axis=1)) <= 1e-6 * np.abs(wg).sum(axis=1))
+
+
 def test_weights_without_given_stencils_runs_knn(lib, sphere):
     X, nrm, idx = sphere
     res = lib.build_weights(dev(X), dev(nrm), 31, eps_mode="fixed", eps=4.0)
@@ -197,7 +226,7 @@ def test_argument_errors(lib):
         lib.build_weights(dev(X), dev(nrm), 31, degree=3)
     X2, nrm2 = fibonacci_sphere(200)
     with pytest.raises(lib.RbffdError):
-        lib.build_weights(dev(X2), dev(nrm2), 60)        # n + border > 64 on this path
+        lib.build_weights(dev(X2), dev(nrm2), 119)       # n + border = 129 > 128
     with pytest.raises(lib.RbffdError):
         lib.build_weights(dev(X2), dev(nrm2), 31, eps_mode="given")   # eps_in missing
     Xe = np.zeros((0, 3))
