@@ -49,6 +49,30 @@ def rk4_bytes_per_step(N, n, species=2, fp=4, ip=4):
     return mat + vec
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_rk4_stage_blob_N1e6_n50.md")
+
+
+def measured_traffic():
+    """HBM bytes per k_rk4_stage launch from the committed counter profile
+    (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or None when
+    the stepper source has changed since it was measured."""
+    import hashlib
+    import re
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^traffic: (\{.*\})$", text, re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = open(os.path.join(ROOT, "paper_1404_0812_amd", "csrc", "step.hip"), "rb").read()
+    if hashlib.sha1(src).hexdigest() != rec.get("source_sha1"):
+        return None
+    return rec
+
+
 def spectral_radius(op, N, iters=300, seed=5):
     import torch
 
@@ -227,12 +251,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read_per_copy": a.numel() * 4,
+                          "bytes_written_per_copy": b.numel() * 4, "copies": 5}), flush=True)
+        return
 
     import paper_1404_0812_amd as rb
     from paper_1404_0812_amd import learned
@@ -339,8 +375,11 @@ def main():
     rk4_gbs = bytes_step / (ms_rk4 / 1e3) / 1e9
     roof_w = {"bound": "alu", "achieved": w_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
               "frac": w_tflops / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_weights (FP64 VALU)"}
+    tr = measured_traffic()
     roof_s = {"bound": "hbm", "achieved": rk4_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rk4_stage (sliced-ELL SpMV + RK4)"}
+              "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": tr["bytes_per_launch"] if tr else None,
+              "algorithmic_bytes_per_launch": bytes_step / 4, "launches_per_step": 4,
+              "kernel": "k_rk4_stage (sliced-ELL SpMV + RK4)"}
     dominant_is_rk4 = med["rk4"] >= med["weights"]
 
     def growth_rate(w_tensor, idx_t, perm_t):
