@@ -39,14 +39,18 @@ def weights_flops(n, r, evals):
     return evals * (4.0 / 3.0 * m ** 3 + 10.0 * n * n) + 30.0 * m * m + 40.0 * n * n
 
 
-def rk4_bytes_per_step(N, n, species=2, fp=4, ip=4):
-    """Algorithmic HBM bytes of one FP32 RK4 step (4 stage kernels): each stage
-    streams the (n-1) off-diagonal indices and weights of every row, and per
-    row reads/writes the species values: stage inputs 24/40/40/32 B for two
-    FP32 species (gathered input once, own state, accumulator, next input)."""
-    mat = 4 * N * (n - 1) * (fp + ip)
-    vec = N * species * fp * (3 + 5 + 5 + 4)
-    return mat + vec
+def rk4_bytes_per_step(N, n, stats=None, species=2):
+    """Algorithmic HBM bytes of one FP32 RK4 step (4 stage kernels).  Each
+    stage streams, per row, the n-1 off-diagonal FP32 weights and their column
+    entries: 2-byte positions in the slice's halo list for rows of slices whose
+    halo is staged in LDS (plus 4 bytes per halo-list entry), 4-byte row
+    indices for the others; and per row the species values: stage inputs
+    24/40/40/32 B for two FP32 species (stage input once, own state,
+    accumulator, next input).  stats = Operator.stats()."""
+    hr, he = (stats[2], stats[3]) if stats else (0, 0)
+    mat = hr * (n - 1) * (4 + 2) + (N - hr) * (n - 1) * (4 + 4) + he * 4
+    vec = N * species * 4 * (3 + 5 + 5 + 4)
+    return 4 * mat + vec
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_rk4_stage_blob_N1e6_n50.md")
@@ -202,8 +206,12 @@ def batched_section(rb, ctx, kappa_T=1e12, count=64, diffusion_steps=1000, seed=
     b = ev()
     torch.cuda.synchronize()
     ms_step = a.elapsed_time(b) / diffusion_steps
-    slots = sum(int(s[0].shape[0]) * (s[2] - 1) for s in surfs)
-    step_bytes = 4 * slots * 8 + total * 4 * (3 + 5 + 5 + 4)
+    nsl, hs, hr, he = op.stats()
+    # single species: per stage the n-1 weights + column entries per row, halo lists, 4 B state values
+    rows_n = [(int(s[0].shape[0]), s[2]) for s in surfs]
+    slots = sum(N_ * (n_ - 1) for N_, n_ in rows_n)
+    halo_frac = hr / total
+    step_bytes = 4 * (slots * 4 + slots * (2 * halo_frac + 4 * (1 - halo_frac)) + he * 4) + total * 4 * (3 + 5 + 5 + 4)
     ns = {}
     for _, _, n in surfs:
         ns[str(n)] = ns.get(str(n), 0) + 1
@@ -214,6 +222,7 @@ def batched_section(rb, ctx, kappa_T=1e12, count=64, diffusion_steps=1000, seed=
             "status_counts": {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
             "median_log10_kappa": float(np.median(np.log10(kap[np.isfinite(kap)]))),
             "diffusion": {"steps": diffusion_steps, "dt": dt, "rho_L": rho, "prec": "f32",
+                          "operator_stats": {"slices": nsl, "halo_slices": hs, "halo_rows": hr, "halo_entries": he},
                           "ms_per_step": ms_step, "achieved_GBs": step_bytes / (ms_step / 1e3) / 1e9,
                           "state_finite": bool(torch.isfinite(out).all().item())}}
 
@@ -339,6 +348,8 @@ def main():
         e2 = ev()
         op = rb.Operator(idx, res.w, perm=perm, ctx=ctx)
         e3 = ev()
+        if timed:
+            op_stats = op.stats()
         if dt_rk4 is None:
             # RK4 stability (real-axis interval 2.785): dt = 0.5 * 2.785 / (D_max rho(L)),
             # rho(L) from 300 power iterations with the library's operator (setup,
@@ -371,7 +382,7 @@ def main():
     r_border = 10
     flops = float(np.sum(weights_flops(n, r_border, nevals.astype(np.float64))))
     w_tflops = flops / (med["weights"] / 1e3) / 1e12
-    bytes_step = rk4_bytes_per_step(args.N, n)
+    bytes_step = rk4_bytes_per_step(args.N, n, op_stats)
     rk4_gbs = bytes_step / (ms_rk4 / 1e3) / 1e9
     roof_w = {"bound": "alu", "achieved": w_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
               "frac": w_tflops / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_weights (FP64 VALU)"}
@@ -379,7 +390,9 @@ def main():
     roof_s = {"bound": "hbm", "achieved": rk4_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": tr["bytes_per_launch"] if tr else None,
               "algorithmic_bytes_per_launch": bytes_step / 4, "launches_per_step": 4,
-              "kernel": "k_rk4_stage (sliced-ELL SpMV + RK4)"}
+              "kernel": "k_rk4_stage (sliced-ELL SpMV with LDS-staged halo + RK4)",
+              "operator_stats": {"slices": op_stats[0], "halo_slices": op_stats[1], "halo_rows": op_stats[2],
+                                 "mean_halo": op_stats[3] / max(1, op_stats[1])}}
     dominant_is_rk4 = med["rk4"] >= med["weights"]
 
     def growth_rate(w_tensor, idx_t, perm_t):

@@ -230,6 +230,14 @@ typedef struct {
 int rbffd_op_create_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_op_surface* surf, rbffd_op* out);
 int rbffd_op_destroy(rbffd_op op);
 
+/* Layout statistics of an operator (HOST outputs, each nullable): slices of
+ * 64 rows; slices whose FP32 stage reads neighbour values from a halo staged
+ * in LDS (at most 640 distinct neighbour rows; the others gather directly),
+ * the rows in those slices, and their total halo entries.  Synchronises the
+ * context's stream. */
+int rbffd_op_stats(rbffd_op op, int64_t* nslices, int64_t* halo_slices, int64_t* halo_rows,
+                   int64_t* halo_entries);
+
 /*
  * One operator application Lu = L_X u (caller order, FP64 in and out),
  * computed in FP64 (plain form sum_j w_ij u_j) or FP32 (difference form).

@@ -329,6 +329,12 @@ class Operator:
         except Exception:
             pass
 
+    def stats(self):
+        """(slices, slices with an LDS-staged halo, rows in them, halo entries)."""
+        v = [ctypes.c_int64() for _ in range(4)]
+        self.ctx.check(self.ctx.lib.rbffd_op_stats(self.h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
     def apply(self, u, prec="f64"):
         u = _dev(u, torch.float64, "u")
         out = torch.empty_like(u)

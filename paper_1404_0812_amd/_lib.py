@@ -102,6 +102,8 @@ SIGNATURES = {
     "rbffd_op_create": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p,
                                   ctypes.POINTER(c_void_p)]),
     "rbffd_op_destroy": (c_int32, [c_void_p]),
+    "rbffd_op_stats": (c_int32, [c_void_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int64), ctypes.POINTER(c_int64),
+                                 ctypes.POINTER(c_int64)]),
     "rbffd_op_create_batched": (c_int32, [c_void_p, c_int32, ctypes.POINTER(OpSurface), ctypes.POINTER(c_void_p)]),
     "rbffd_build_weights_batched": (c_int32, [c_void_p, c_int32, ctypes.POINTER(Surface), ctypes.POINTER(WeightOpts),
                                               ctypes.POINTER(BatchTuning)]),

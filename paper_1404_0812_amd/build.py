@@ -1,6 +1,6 @@
 """Build librbffd.so for gfx950 with hipcc (in-tree, next to this file).
 
-    python -m paper_1404_0812_amd.build [--verbose]
+    python -m paper_1404_0812_amd.build [--verbose] [--incremental]
 """
 from __future__ import annotations
 
@@ -41,9 +41,17 @@ def hipcc():
     return "hipcc"
 
 
-def _compile(entry, verbose: bool) -> str:
+def _newest_dependency(src: str) -> float:
+    deps = [os.path.join(CSRC, src), os.path.join(INCLUDE, "rbffd.h"), os.path.abspath(__file__)]
+    deps += [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    return max(os.path.getmtime(d) for d in deps)
+
+
+def _compile(entry, verbose: bool, incremental: bool = False) -> str:
     src, name, defines = entry
     obj = os.path.join(BUILD, name + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_dependency(src):
+        return obj
     cmd = [hipcc(), "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC]
     cmd += DEVICE_FLAGS + defines
     if src.endswith(".hip"):
@@ -62,10 +70,12 @@ def _compile(entry, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental=True: only those older than their
+    source or any header) and link librbffd.so."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
@@ -78,4 +88,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="--verbose" in sys.argv))
+    print(build(verbose="--verbose" in sys.argv, incremental="--incremental" in sys.argv))

@@ -28,7 +28,12 @@ struct OpSlice {
     int64_t off32;  // element offset in the FP32 off-diagonal arrays (n - 1 slots)
     int32_t n;      // stencil size of the slice's rows
     int32_t rows;   // rows in use (64 except at a surface's end)
+    int32_t halo;   // FP32 path: distinct neighbour rows of the slice (<= OP_HALO_MAX), -1: too many
+    int32_t pad;
 };
+
+// Largest slice neighbourhood staged in LDS by the FP32 stage kernels.
+constexpr int OP_HALO_MAX = 640;
 
 struct rbffd_op_s {
     rbffd_ctx ctx = nullptr;
@@ -42,6 +47,8 @@ struct rbffd_op_s {
     double* w64 = nullptr;
     int32_t* idx32 = nullptr;     // FP32 difference form: off-diagonal slots 1..n-1 at off32 + 64 (k-1) + r
     float* w32 = nullptr;
+    uint16_t* lidx = nullptr;     // FP32 path: slot entries as positions in the slice's halo list
+    int32_t* halo = nullptr;      // FP32 path: OP_HALO_MAX sorted distinct neighbour rows per slice
     int32_t* perm = nullptr;      // internal row -> caller row (-1 for padding), P entries
     // state workspace (internal order), allocated on first step
     void* work = nullptr;

@@ -29,6 +29,15 @@ namespace {
 
 constexpr int BLK = 256;
 
+// Element offset, inside a slice of `ns` slots, of slot k of lane r: the first
+// 4 (ns / 4) slots go in groups of four with a lane's four slots adjacent (one
+// 16-byte load per lane for FP32, two for FP64), the remaining slots one
+// 64-element run each.  A slice holds 64 ns elements either way.
+__host__ __device__ __forceinline__ int64_t slot_pos(int k, int ns, int r) {
+    const int G = ns >> 2;
+    return k < 4 * G ? 256 * (int64_t)(k >> 2) + 4 * r + (k & 3) : 256 * (int64_t)G + 64 * (int64_t)(k - 4 * G) + r;
+}
+
 // iperm[perm[p]] = p for one surface (perm nullable: identity)
 __global__ void k_inverse_perm(int64_t N, const int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -51,14 +60,97 @@ __global__ void k_build_sell(int64_t N, int n, int64_t row0, int64_t col0, const
     for (int k = 0; k < n; ++k) {
         const int32_t j = (int32_t)(row0 + iperm[idx[i * n + k]]);
         const double wk = w[i * n + k];
-        idx64[sl.off64 + 64 * k + r] = j;
-        w64[sl.off64 + 64 * k + r] = wk;
+        const int64_t q64 = sl.off64 + slot_pos(k, n, r);
+        idx64[q64] = j;
+        w64[q64] = wk;
         if (k > 0) {
-            idx32[sl.off32 + 64 * (k - 1) + r] = j;
-            w32[sl.off32 + 64 * (k - 1) + r] = (float)wk;
+            const int64_t q32 = sl.off32 + slot_pos(k - 1, n - 1, r);
+            idx32[q32] = j;
+            w32[q32] = (float)wk;
         }
     }
     gperm[q] = (int32_t)(col0 + i);
+}
+
+// Halo of each slice for the FP32 path: the sorted distinct rows its 64 rows
+// read (off-diagonal slots), and every slot entry rewritten as a position in
+// that list.  One 256-thread block per slice: the <= 64 x 127 entries are
+// sorted in LDS (bitonic), de-duplicated with a block scan, and each entry is
+// located in the unique list by binary search.  Slices with more than
+// OP_HALO_MAX distinct rows keep halo = -1 and are read directly.
+constexpr int HB_CAP = 8192;  // >= 64 x 127 entries per slice
+
+__global__ __launch_bounds__(256) void k_build_halo(int64_t nslices, OpSlice* __restrict__ slices,
+                                                    const int32_t* __restrict__ idx32, uint16_t* __restrict__ lidx,
+                                                    int32_t* __restrict__ halo) {
+    __shared__ int32_t key[HB_CAP];
+    __shared__ int32_t cnt[256];
+    __shared__ int32_t uniq[OP_HALO_MAX];
+    const int64_t s = blockIdx.x;
+    if (s >= nslices) return;
+    const OpSlice sl = slices[s];
+    const int ns = sl.n - 1, rows = sl.rows, E = rows * ns, tid = threadIdx.x;
+    for (int i = tid; i < HB_CAP; i += 256)
+        key[i] = i < E ? idx32[sl.off32 + slot_pos(i % ns, ns, i / ns)] : 0x7fffffff;
+    __syncthreads();
+    for (int size = 2; size <= HB_CAP; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < HB_CAP / 2; i += 256) {
+                const int lo = 2 * i - (i & (stride - 1));  // first of the pair (stride apart)
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const int a = key[lo], b = key[hi];
+                if ((a > b) == up) {
+                    key[lo] = b;
+                    key[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // distinct keys among the E sorted entries: thread t counts its 32 consecutive ones
+    constexpr int PER = HB_CAP / 256;
+    int c = 0;
+    for (int q = 0; q < PER; ++q) {
+        const int i = tid * PER + q;
+        c += (i < E && (i == 0 || key[i] != key[i - 1])) ? 1 : 0;
+    }
+    cnt[tid] = c;
+    __syncthreads();
+    if (tid == 0) {
+        int run = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int v = cnt[t];
+            cnt[t] = run;
+            run += v;
+        }
+        slices[s].halo = run <= OP_HALO_MAX ? run : -1;
+        key[HB_CAP - 1] = run <= OP_HALO_MAX ? run : -1;  // E < HB_CAP: the last slot is padding
+    }
+    __syncthreads();
+    const int H = key[HB_CAP - 1];
+    if (H < 0) return;
+    int pos = cnt[tid];
+    for (int q = 0; q < PER; ++q) {
+        const int i = tid * PER + q;
+        if (i < E && (i == 0 || key[i] != key[i - 1])) {
+            uniq[pos] = key[i];
+            halo[s * OP_HALO_MAX + pos] = key[i];
+            ++pos;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < E; i += 256) {
+        const int64_t at = sl.off32 + slot_pos(i % ns, ns, i / ns);
+        const int32_t j = idx32[at];
+        int lo = 0, hi = H - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (uniq[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        lidx[at] = (uint16_t)lo;
+    }
 }
 
 // State lives species-interleaved in internal order: element (p, s) at p*S + s,
@@ -108,6 +200,8 @@ __device__ __forceinline__ void reaction(const T (&y)[2], T (&r)[2], const React
 struct StageArgs {
     int64_t nslices;
     const OpSlice* slices;
+    const uint16_t* lidx;   // FP32 path: halo positions of the slot entries
+    const int32_t* halo;    // FP32 path: halo lists (OP_HALO_MAX per slice)
     double D[2];
     double dt;
     ReactParams rp;
@@ -156,13 +250,14 @@ __device__ __forceinline__ void vstore(T* __restrict__ Y, int64_t j, const T (&v
     }
 }
 
-constexpr int CHUNK = 8;
-
 // Row of the calling thread: slice and lane.  Four slices per 256-thread block.
 struct RowPos {
-    int64_t p;    // internal row
-    int64_t off;  // element offset of the row's slot 0 (precision's array)
-    int ns;       // slots to read
+    int64_t p;      // internal row
+    int64_t slice;  // -1: past the last slice (the whole wavefront)
+    int64_t base;   // element offset of the slice (precision's array)
+    int lane;
+    int ns;         // slots to read
+    int halo;       // FP32: halo size, or -1 (direct gathers)
     bool live;
 };
 
@@ -170,69 +265,168 @@ template <typename T>
 __device__ __forceinline__ RowPos row_pos(const StageArgs& a) {
     RowPos rp;
     const int64_t slice = (int64_t)xcd_block() * (BLK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    rp.p = slice * 64 + lane;
+    rp.lane = threadIdx.x & 63;
+    rp.p = slice * 64 + rp.lane;
     rp.live = false;
-    rp.off = 0;
+    rp.base = 0;
     rp.ns = 0;
+    rp.halo = -1;
+    rp.slice = -1;
     if (slice >= a.nslices) return rp;
     const OpSlice sl = a.slices[slice];
-    if (lane >= sl.rows) return rp;
     constexpr bool f32 = sizeof(T) == 4;
-    rp.live = true;
-    rp.off = (f32 ? sl.off32 : sl.off64) + lane;
+    rp.slice = slice;
+    rp.live = rp.lane < sl.rows;
+    rp.base = f32 ? sl.off32 : sl.off64;
     rp.ns = f32 ? sl.n - 1 : sl.n;
+    rp.halo = f32 ? sl.halo : -1;
     return rp;
 }
 
-// L applied to the stage input of row rp.p.  FP32: difference form over the
-// n-1 off-diagonal slots; FP64: plain form over all n slots in slot order.
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// four consecutive slots of one lane (streamed once: non-temporal)
+__device__ __forceinline__ void load4(const int32_t* ix, const float* wx, int (&j)[4], float (&w)[4]) {
+    const i4v jv = __builtin_nontemporal_load(reinterpret_cast<const i4v*>(ix));
+    const f4v wv = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(wx));
+    j[0] = jv.x; j[1] = jv.y; j[2] = jv.z; j[3] = jv.w;
+    w[0] = wv.x; w[1] = wv.y; w[2] = wv.z; w[3] = wv.w;
+}
+__device__ __forceinline__ void load4(const int32_t* ix, const double* wx, int (&j)[4], double (&w)[4]) {
+    const i4v jv = __builtin_nontemporal_load(reinterpret_cast<const i4v*>(ix));
+    const d2v w0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(wx));
+    const d2v w1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(wx) + 1);
+    j[0] = jv.x; j[1] = jv.y; j[2] = jv.z; j[3] = jv.w;
+    w[0] = w0.x; w[1] = w0.y; w[2] = w1.x; w[3] = w1.y;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void accumulate(const T* __restrict__ Y, int j, T wk, const T (&yi)[2], T& s0, T& s1) {
+    constexpr bool diff = sizeof(T) == 4;
+    T y[2];
+    vload<T, S>(Y, j, y);
+    if (diff) {
+        s0 = fma(wk, y[0] - yi[0], s0);
+        if (S == 2) s1 = fma(wk, y[1] - yi[1], s1);
+    } else {
+        s0 = fma(wk, y[0], s0);
+        if (S == 2) s1 = fma(wk, y[1], s1);
+    }
+}
+
+// L applied to the stage input of row rp.p, in slot order.  FP32: difference
+// form over the n-1 off-diagonal slots; FP64: plain form over all n slots.
 template <typename T, int S>
 __device__ __forceinline__ void apply_row(const RowPos& rp, const int32_t* __restrict__ idx,
                                           const T* __restrict__ w, const T* __restrict__ Y, const T (&yi)[2],
                                           T (&acc)[2]) {
     const int ns = rp.ns;
-    const int32_t* ix = idx + rp.off;
-    const T* wx = w + rp.off;
-    constexpr bool diff = sizeof(T) == 4;
+    const int G = ns >> 2;
+    const int32_t* ix = idx + rp.base + 4 * rp.lane;
+    const T* wx = w + rp.base + 4 * rp.lane;
     T s0 = 0, s1 = 0;
-    int k0 = 0;
-    for (; k0 + CHUNK <= ns; k0 += CHUNK) {
-        int j[CHUNK];
-        T wk[CHUNK];
+    int g = 0;
+    for (; g + 2 <= G; g += 2) {  // eight slots in flight
+        int j[8];
+        T wk[8];
+        load4(ix + 256 * g, wx + 256 * g, *reinterpret_cast<int(*)[4]>(j), *reinterpret_cast<T(*)[4]>(wk));
+        load4(ix + 256 * (g + 1), wx + 256 * (g + 1), *reinterpret_cast<int(*)[4]>(j + 4),
+              *reinterpret_cast<T(*)[4]>(wk + 4));
 #pragma unroll
-        for (int t = 0; t < CHUNK; ++t) {
-            j[t] = __builtin_nontemporal_load(ix + 64 * (k0 + t));
-            wk[t] = __builtin_nontemporal_load(wx + 64 * (k0 + t));
-        }
+        for (int t = 0; t < 8; ++t) accumulate<T, S>(Y, j[t], wk[t], yi, s0, s1);
+    }
+    if (g < G) {
+        int j[4];
+        T wk[4];
+        load4(ix + 256 * g, wx + 256 * g, j, wk);
 #pragma unroll
-        for (int t = 0; t < CHUNK; ++t) {
-            T y[2];
-            vload<T, S>(Y, j[t], y);
-            if (diff) {
-                s0 = fma(wk[t], y[0] - yi[0], s0);
-                if (S == 2) s1 = fma(wk[t], y[1] - yi[1], s1);
-            } else {
-                s0 = fma(wk[t], y[0], s0);
-                if (S == 2) s1 = fma(wk[t], y[1], s1);
-            }
-        }
+        for (int t = 0; t < 4; ++t) accumulate<T, S>(Y, j[t], wk[t], yi, s0, s1);
     }
-    for (int k = k0; k < ns; ++k) {
-        const int j = __builtin_nontemporal_load(ix + 64 * k);
-        const T wk = __builtin_nontemporal_load(wx + 64 * k);
-        T y[2];
-        vload<T, S>(Y, j, y);
-        if (diff) {
-            s0 = fma(wk, y[0] - yi[0], s0);
-            if (S == 2) s1 = fma(wk, y[1] - yi[1], s1);
-        } else {
-            s0 = fma(wk, y[0], s0);
-            if (S == 2) s1 = fma(wk, y[1], s1);
-        }
-    }
+    const int32_t* ir = idx + rp.base + 256 * G + rp.lane;
+    const T* wr = w + rp.base + 256 * G + rp.lane;
+    for (int t = 0; t < ns - 4 * G; ++t)
+        accumulate<T, S>(Y, __builtin_nontemporal_load(ir + 64 * t), __builtin_nontemporal_load(wr + 64 * t), yi,
+                         s0, s1);
     acc[0] = s0;
     acc[1] = s1;
+}
+
+typedef unsigned short u4v __attribute__((ext_vector_type(4)));
+
+// Stage the slice's halo values (all 64 lanes of the wavefront take part).
+template <int S>
+__device__ __forceinline__ void load_halo(const RowPos& rp, const int32_t* __restrict__ halo,
+                                          const float* __restrict__ Y, typename Vec<float, S>::type* ylds) {
+    const int32_t* h = halo + rp.slice * OP_HALO_MAX;
+    for (int t = rp.lane; t < rp.halo; t += 64) ylds[t] = reinterpret_cast<const typename Vec<float, S>::type*>(Y)[h[t]];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int S>
+__device__ __forceinline__ void halo_value(const typename Vec<float, S>::type* ylds, int l, float (&y)[2]) {
+    if constexpr (S == 2) {
+        const float2 v = ylds[l];
+        y[0] = v.x;
+        y[1] = v.y;
+    } else {
+        y[0] = ylds[l];
+        y[1] = 0.0f;
+    }
+}
+
+// FP32 difference form over the n-1 off-diagonal slots, neighbour values from
+// the staged halo (same slot order as apply_row).
+template <int S>
+__device__ __forceinline__ void apply_row_halo(const RowPos& rp, const uint16_t* __restrict__ lidx,
+                                               const float* __restrict__ w, const typename Vec<float, S>::type* ylds,
+                                               const float (&yi)[2], float (&acc)[2]) {
+    const int ns = rp.ns;
+    const int G = ns >> 2;
+    const uint16_t* lx = lidx + rp.base + 4 * rp.lane;
+    const float* wx = w + rp.base + 4 * rp.lane;
+    float s0 = 0.0f, s1 = 0.0f;
+    auto acc1 = [&](int l, float wk) {
+        float y[2];
+        halo_value<S>(ylds, l, y);
+        s0 = fma(wk, y[0] - yi[0], s0);
+        if (S == 2) s1 = fma(wk, y[1] - yi[1], s1);
+    };
+    for (int g = 0; g < G; ++g) {
+        const u4v lv = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(lx + 256 * g));
+        const f4v wv = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(wx + 256 * g));
+        acc1(lv.x, wv.x);
+        acc1(lv.y, wv.y);
+        acc1(lv.z, wv.z);
+        acc1(lv.w, wv.w);
+    }
+    const uint16_t* lr = lidx + rp.base + 256 * G + rp.lane;
+    const float* wr = w + rp.base + 256 * G + rp.lane;
+    for (int t = 0; t < ns - 4 * G; ++t) acc1(__builtin_nontemporal_load(lr + 64 * t), __builtin_nontemporal_load(wr + 64 * t));
+    acc[0] = s0;
+    acc[1] = s1;
+}
+
+// L applied to the stage input of row rp.p: FP32 through the staged halo when
+// the slice has one, otherwise (and in FP64) by direct gathers.  Every lane of
+// the wavefront must call this (the halo is loaded cooperatively).
+template <typename T, int S>
+__device__ __forceinline__ void laplacian_row(const StageArgs& a, const RowPos& rp, const int32_t* __restrict__ idx,
+                                              const T* __restrict__ w, const T* __restrict__ Y, const T (&yi)[2],
+                                              T (&lap)[2]) {
+    if constexpr (sizeof(T) == 4) {
+        __shared__ typename Vec<float, S>::type ylds[BLK / 64][OP_HALO_MAX];
+        if (rp.halo >= 0) {
+            auto* yl = ylds[threadIdx.x >> 6];
+            load_halo<S>(rp, a.halo, Y, yl);
+            if (rp.live) apply_row_halo<S>(rp, a.lidx, w, yl, yi, lap);
+            return;
+        }
+    }
+    if (rp.live) apply_row<T, S>(rp, idx, w, Y, yi, lap);
 }
 
 // RK4 stage `ST` (0..3).  Y: stage input; U: state at the start of the step;
@@ -242,12 +436,13 @@ __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* _
                                                    const T* __restrict__ w, const T* __restrict__ Y,
                                                    T* __restrict__ U, T* __restrict__ ACC, T* __restrict__ YN) {
     const RowPos rp = row_pos<T>(a);
-    if (!rp.live) return;
+    if (rp.slice < 0) return;  // the whole wavefront
     const int64_t p = rp.p;
-    T yi[2];
-    vload<T, S>(Y, p, yi);
+    T yi[2] = {0, 0};
+    if (rp.live) vload<T, S>(Y, p, yi);
     T lap[2];
-    apply_row<T, S>(rp, idx, w, Y, yi, lap);
+    laplacian_row<T, S>(a, rp, idx, w, Y, yi, lap);
+    if (!rp.live) return;
     T r[2];
     reaction<T, R>(yi, r, a.rp);
     T k[2];
@@ -285,12 +480,12 @@ template <typename T>
 __global__ __launch_bounds__(BLK) void k_apply(StageArgs a, const int32_t* __restrict__ idx, const T* __restrict__ w,
                                                const T* __restrict__ Y, T* __restrict__ out) {
     const RowPos rp = row_pos<T>(a);
-    if (!rp.live) return;
-    T yi[2];
-    vload<T, 1>(Y, rp.p, yi);
+    if (rp.slice < 0) return;  // the whole wavefront
+    T yi[2] = {0, 0};
+    if (rp.live) vload<T, 1>(Y, rp.p, yi);
     T lap[2];
-    apply_row<T, 1>(rp, idx, w, Y, yi, lap);
-    out[rp.p] = lap[0];
+    laplacian_row<T, 1>(a, rp, idx, w, Y, yi, lap);
+    if (rp.live) out[rp.p] = lap[0];
 }
 
 // blocks of one stage launch: four slices each
@@ -363,6 +558,8 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
             o.off32 = off32;
             o.n = n;
             o.rows = (int32_t)std::min<int64_t>(64, Ns - r);
+            o.halo = -1;
+            o.pad = 0;
             sl.push_back(o);
             off64 += 64 * (int64_t)n;
             off32 += 64 * (int64_t)(n - 1);
@@ -386,6 +583,8 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
               hipMalloc(&op->w64, std::max<int64_t>(1, off64) * sizeof(double)) == hipSuccess &&
               hipMalloc(&op->idx32, std::max<int64_t>(1, off32) * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&op->w32, std::max<int64_t>(1, off32) * sizeof(float)) == hipSuccess &&
+              hipMalloc(&op->lidx, std::max<int64_t>(1, off32) * sizeof(uint16_t)) == hipSuccess &&
+              hipMalloc(&op->halo, std::max<size_t>(1, sl.size()) * OP_HALO_MAX * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&op->perm, std::max<int64_t>(1, P) * sizeof(int32_t)) == hipSuccess;
     int32_t* iperm = nullptr;
     ok = ok && hipMalloc(&iperm, std::max<int64_t>(1, maxN) * sizeof(int32_t)) == hipSuccess;
@@ -404,6 +603,11 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
         hipLaunchKernelGGL(k_inverse_perm, g, b, 0, st, Ns, surf[s].perm, iperm);
         hipLaunchKernelGGL(k_build_sell, g, b, 0, st, Ns, surf[s].n, row0[s], col0[s], surf[s].idx, surf[s].w,
                            surf[s].perm, iperm, op->slices, op->idx64, op->w64, op->idx32, op->w32, op->perm);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && !sl.empty()) {
+        hipLaunchKernelGGL(k_build_halo, dim3((unsigned)sl.size()), dim3(256), 0, st, (int64_t)sl.size(), op->slices,
+                           op->idx32, op->lidx, op->halo);
         e = hipGetLastError();
     }
     // the slice table comes from pageable host memory and iperm is reused per surface: wait here
@@ -463,9 +667,33 @@ extern "C" int rbffd_op_destroy(rbffd_op op) {
     if (op->w64) (void)hipFree(op->w64);
     if (op->idx32) (void)hipFree(op->idx32);
     if (op->w32) (void)hipFree(op->w32);
+    if (op->lidx) (void)hipFree(op->lidx);
+    if (op->halo) (void)hipFree(op->halo);
     if (op->perm) (void)hipFree(op->perm);
     if (op->work) (void)hipFree(op->work);
     delete op;
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_op_stats(rbffd_op op, int64_t* nslices, int64_t* halo_slices, int64_t* halo_rows,
+                              int64_t* halo_entries) {
+    if (!op) return RBFFD_E_ARG;
+    std::vector<OpSlice> sl((size_t)op->nslices);
+    if (!sl.empty()) {
+        HIP_TRY(op->ctx, hipStreamSynchronize(op->ctx->stream));
+        HIP_TRY(op->ctx, hipMemcpy(sl.data(), op->slices, sl.size() * sizeof(OpSlice), hipMemcpyDeviceToHost));
+    }
+    int64_t hs = 0, hr = 0, he = 0;
+    for (const OpSlice& o : sl)
+        if (o.halo >= 0) {
+            ++hs;
+            hr += o.rows;
+            he += o.halo;
+        }
+    if (nslices) *nslices = op->nslices;
+    if (halo_slices) *halo_slices = hs;
+    if (halo_rows) *halo_rows = hr;
+    if (halo_entries) *halo_entries = he;
     return RBFFD_OK;
 }
 
@@ -482,6 +710,8 @@ extern "C" int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const doubl
     std::memset(&a, 0, sizeof(a));
     a.nslices = op->nslices;
     a.slices = op->slices;
+    a.lidx = op->lidx;
+    a.halo = op->halo;
     if (prec == RBFFD_F64) {
         double* Y = (double*)op->work;
         double* out = Y + P;
@@ -521,6 +751,8 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     std::memset(&a, 0, sizeof(a));
     a.nslices = op->nslices;
     a.slices = op->slices;
+    a.lidx = op->lidx;
+    a.halo = op->halo;
     a.D[0] = D[0];
     a.D[1] = nspecies == 2 ? D[1] : 0.0;
     a.dt = dt;
