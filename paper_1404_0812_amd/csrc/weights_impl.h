@@ -402,61 +402,76 @@ __device__ __forceinline__ double spectrum_min_abs(const Shared<NB>& S, int lane
 }
 
 // ------------------------------------------------------- tridiagonal solve ----
-// Gaussian elimination with partial pivoting of T (one thread); false on a zero pivot.
+// Gaussian elimination with partial pivoting of T (one thread); false on a
+// zero pivot.  The diagonal and super-diagonal of the row being eliminated are
+// carried in registers, so each step reads LDS only for inputs that do not
+// depend on the previous step.
 template <int NB>
 __device__ __forceinline__ bool tri_factor(Shared<NB>& S) {
     const int m = S.m;
-    for (int i = 0; i < m; ++i) {
-        S.fd[i] = S.d[i];
-        S.fdu[i] = i < m - 1 ? S.e[i] : 0.0;
-        S.fdl[i] = i < m - 1 ? S.e[i] : 0.0;  // sub-diagonal, later the second super-diagonal
-    }
+    double dcur = S.d[0];                      // pivot-row diagonal (after earlier steps)
+    double ucur = m > 1 ? S.e[0] : 0.0;        // its super-diagonal
     for (int i = 0; i < m - 1; ++i) {
-        const double sub = S.fdl[i];
-        if (fabs(S.fd[i]) >= fabs(sub)) {
-            if (S.fd[i] == 0.0) return false;
-            const double f = sub / S.fd[i];
-            S.fd[i + 1] -= f * S.fdu[i];
+        const double sub = S.e[i];             // sub-diagonal entry below the pivot
+        const double dnext = S.d[i + 1];
+        const double unext = i < m - 2 ? S.e[i + 1] : 0.0;
+        if (fabs(dcur) >= fabs(sub)) {
+            if (dcur == 0.0) return false;
+            const double f = sub / dcur;
+            S.fd[i] = 1.0 / dcur;              // reciprocal of the pivot
+            S.fdu[i] = ucur;
             S.fdl[i] = 0.0;
             S.ffact[i] = f;
             S.fswap[i] = 0;
-        } else {
-            const double f = S.fd[i] / sub;
-            S.fd[i] = sub;
-            const double tmp = S.fd[i + 1];
-            S.fd[i + 1] = S.fdu[i] - f * tmp;
-            if (i < m - 2) {
-                S.fdl[i] = S.fdu[i + 1];
-                S.fdu[i + 1] = -f * S.fdl[i];
-            } else {
-                S.fdl[i] = 0.0;
-            }
-            S.fdu[i] = tmp;
+            dcur = dnext - f * ucur;
+            ucur = unext;
+        } else {                               // swap rows i and i + 1
+            const double f = dcur / sub;
+            S.fd[i] = 1.0 / sub;
+            S.fdu[i] = dnext;
+            S.fdl[i] = i < m - 2 ? unext : 0.0;  // second super-diagonal
             S.ffact[i] = f;
             S.fswap[i] = 1;
+            dcur = ucur - f * dnext;
+            ucur = i < m - 2 ? -f * unext : unext;
         }
     }
-    if (S.fd[m - 1] == 0.0) return false;
-    for (int i = 0; i < m; ++i) S.fd[i] = 1.0 / S.fd[i];  // keep reciprocals of the pivots
+    if (dcur == 0.0) return false;
+    S.fd[m - 1] = 1.0 / dcur;
+    S.fdu[m - 1] = 0.0;
+    S.fdl[m - 1] = 0.0;
     return true;
 }
 
+// b <- T^{-1} b with the factors of tri_factor (one thread); the running
+// entries of b are carried in registers.
 template <int NB>
 __device__ __forceinline__ void tri_solve(const Shared<NB>& S, double* b) {
     const int m = S.m;
+    double bi = b[0];
     for (int i = 0; i < m - 1; ++i) {
         const double f = S.ffact[i];
+        const double bn = b[i + 1];
         if (!S.fswap[i]) {
-            b[i + 1] -= f * b[i];
+            b[i] = bi;
+            bi = bn - f * bi;
         } else {
-            const double tt = b[i];
-            b[i] = b[i + 1];
-            b[i + 1] = tt - f * b[i + 1];
+            b[i] = bn;
+            bi = bi - f * bn;
         }
     }
-    b[m - 1] *= S.fd[m - 1];
-    if (m > 1) b[m - 2] = (b[m - 2] - S.fdu[m - 2] * b[m - 1]) * S.fd[m - 2];
-    for (int i = m - 3; i >= 0; --i) b[i] = (b[i] - S.fdu[i] * b[i + 1] - S.fdl[i] * b[i + 2]) * S.fd[i];
+    double x1 = bi * S.fd[m - 1];  // x_{i+1}
+    b[m - 1] = x1;
+    if (m < 2) return;
+    double x2 = x1;                // x_{i+2}
+    x1 = (b[m - 2] - S.fdu[m - 2] * x2) * S.fd[m - 2];
+    b[m - 2] = x1;
+    for (int i = m - 3; i >= 0; --i) {
+        const double x = (b[i] - S.fdu[i] * x1 - S.fdl[i] * x2) * S.fd[i];
+        b[i] = x;
+        x2 = x1;
+        x1 = x;
+    }
 }
 
 // y <- Q^T y (FWD) or y <- Q y, for NV = 1 or 3 vectors (thread holds component
