@@ -83,7 +83,7 @@ struct Shared {
     double T[RMAX * RMAX];       // monomial coefficients of the border basis T[l*RMAX + k]
     double col[MM], vv[MM], ww[MM], vb[MM];
     double pp[NB][MM];           // matvec partial sums per row block
-    double red[8];               // cross-wave partial sums
+    double red[16];              // cross-wave partial sums, two sets of 8
     double d[MM], e[MM], e2[MM], tau[MM];
     double fd[MM], fdu[MM], fdl[MM], ffact[MM];  // pivoted tridiagonal factors (fd: 1/pivot)
     int fswap[MM];
@@ -101,6 +101,7 @@ struct Tid {
     int cb;    // column block
     int c;     // column index 64 cb + lane
     int tid;   // 0 .. 64 NB^2 - 1 within the stencil's threads
+    mutable int rot = 0;  // reductions done so far (selects the slot set)
 };
 
 template <int NB>
@@ -115,6 +116,12 @@ __device__ __forceinline__ void bsync() {
     }
 }
 
+// Cross-wave partial sums (NB = 2) go through one of two slot sets, taken in
+// turn by successive reductions; every reduction has one barrier between its
+// writes and its reads, so by the time a set is written again every thread
+// has read it, and no second barrier is needed.
+__device__ __forceinline__ double* red_set(double* red, const Tid& t) { return red + 8 * (t.rot++ & 1); }
+
 // Sum over the columns (lane-distributed; each column is held by NB threads).
 template <int NB>
 __device__ __forceinline__ double sum_cols(double v, Shared<NB>& S, const Tid& t) {
@@ -122,11 +129,10 @@ __device__ __forceinline__ double sum_cols(double v, Shared<NB>& S, const Tid& t
     if constexpr (NB == 1) {
         return w;
     } else {
-        if (t.rb == 0 && t.lane == 0) S.red[t.cb] = w;
+        double* red = red_set(S.red, t);
+        if (t.rb == 0 && t.lane == 0) red[t.cb] = w;
         bsync<NB>();
-        const double r = S.red[0] + S.red[1];
-        bsync<NB>();
-        return r;
+        return red[0] + red[1];
     }
 }
 template <int NB>
@@ -135,16 +141,16 @@ __device__ __forceinline__ void sum_cols3(double& a, double& b, double& c, Share
     b = rows_total(row_sum16(b));
     c = rows_total(row_sum16(c));
     if constexpr (NB == 2) {
+        double* red = red_set(S.red, t);
         if (t.rb == 0 && t.lane == 0) {
-            S.red[t.cb] = a;
-            S.red[2 + t.cb] = b;
-            S.red[4 + t.cb] = c;
+            red[t.cb] = a;
+            red[2 + t.cb] = b;
+            red[4 + t.cb] = c;
         }
         bsync<NB>();
-        a = S.red[0] + S.red[1];
-        b = S.red[2] + S.red[3];
-        c = S.red[4] + S.red[5];
-        bsync<NB>();
+        a = red[0] + red[1];
+        b = red[2] + red[3];
+        c = red[4] + red[5];
     }
 }
 // Sum over the rows held by lanes (row 64 rb + lane; cb == 0 waves count).
@@ -154,11 +160,10 @@ __device__ __forceinline__ double sum_rows(double v, Shared<NB>& S, const Tid& t
     if constexpr (NB == 1) {
         return w;
     } else {
-        if (t.cb == 0 && t.lane == 0) S.red[6 + t.rb] = w;
+        double* red = red_set(S.red, t);
+        if (t.cb == 0 && t.lane == 0) red[6 + t.rb] = w;
         bsync<NB>();
-        const double r = S.red[6] + S.red[7];
-        bsync<NB>();
-        return r;
+        return red[6] + red[7];
     }
 }
 template <int NB>
@@ -167,11 +172,10 @@ __device__ __forceinline__ double max_cols(double v, Shared<NB>& S, const Tid& t
     if constexpr (NB == 1) {
         return w;
     } else {
-        if (t.rb == 0 && t.lane == 0) S.red[t.cb] = w;
+        double* red = red_set(S.red, t);
+        if (t.rb == 0 && t.lane == 0) red[t.cb] = w;
         bsync<NB>();
-        const double r = fmax(S.red[0], S.red[1]);
-        bsync<NB>();
-        return r;
+        return fmax(red[0], red[1]);
     }
 }
 

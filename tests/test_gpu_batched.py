@@ -163,3 +163,48 @@ def test_batched_operator_step_matches_per_surface(lib, batch_ops):
                                                        reaction="schnakenberg", params=params, graph_steps=5))
             assert np.array_equal(got[:, off:off + N], ref), prec
             off += N
+
+
+def test_batched_given_and_learned_modes_bitwise(lib, batch):
+    """Per-surface eps arrays (given) and proposals with the kappa-band check
+    (learned) go through the batched launch exactly as through the plain one."""
+    surfs, _ = batch
+    rng = np.random.default_rng(21)
+    eps_in = []
+    for X, nrm, n in surfs:
+        idx, _ = lib.knn(X, n)
+        rho = torch.sqrt(((X[idx.long()] - X[idx[:, :1].long()]) ** 2).sum(-1).max(1).values)
+        eps_in.append(torch.as_tensor(rng.uniform(0.4, 0.9, X.shape[0])).cuda() / rho)
+    for mode, kw in (("given", {}), ("learned", {"kappa_target": 1e12, "band": (1e11, 1e13)})):
+        got = lib.build_weights_batched(surfs, eps_in=eps_in, eps_mode=mode, **kw)
+        for (X, nrm, n), e, g in zip(surfs, eps_in, got):
+            ref = lib.build_weights(X, nrm, n, eps_in=e, eps_mode=mode, **kw)
+            torch.cuda.synchronize()
+            assert _same(g.w, ref.w) and torch.equal(g.eps, ref.eps) and torch.equal(g.status, ref.status), mode
+
+
+def test_batched_edge_surfaces(lib):
+    """An empty surface, a tiny ragged one (N = 130), and the largest system
+    (n = 118 with the degree-2 border, m = 128) in one batch."""
+    from synth import ellipsoid, fibonacci_sphere
+
+    X0 = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    Xa, na = fibonacci_sphere(130)
+    Xb, nb = ellipsoid(1500, 1.0, 0.7, 0.5)
+    surfs = [(X0, X0, 31), (dev(Xa), dev(na), 20), (dev(Xb), dev(nb), 118)]
+    got = lib.build_weights_batched(surfs, eps_mode="bisect", kappa_target=1e10)
+    assert got[0].w.shape == (0, 31)
+    for (X, nrm, n), g in zip(surfs[1:], got[1:]):
+        ref = lib.build_weights(X, nrm, n, eps_mode="bisect", kappa_target=1e10)
+        torch.cuda.synchronize()
+        assert _same(g.w, ref.w) and torch.equal(g.eps, ref.eps)
+        assert torch.all(g.status == 0)
+    # the largest system against the oracle on a few rows
+    idx = host(got[2].idx)
+    eg = host(got[2].eps)
+    rows = np.array([0, 700, 1499])
+    wo = oracle_weights(Xb, nb, idx, eg, rows=rows)
+    wg = host(got[2].w)[rows]
+    k = host(got[2].kappa)[rows]
+    err = np.linalg.norm(wg - wo, axis=1) / np.linalg.norm(wo, axis=1)
+    assert np.all(err <= np.maximum(1e-9, 0.5 * k * 2.0 ** -53)), err
