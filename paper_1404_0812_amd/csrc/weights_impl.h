@@ -586,8 +586,13 @@ __device__ __forceinline__ void solve_refined(const double (&a)[64], Shared<NB>&
 // --------------------------------------------------------------- border ----
 // Monomials in xi (order: 1, x, y, z, x^2, y^2, z^2, xy, xz, yz) at row
 // jr = 64 rb + lane, orthonormalised by MGS with one reorthogonalisation; kept
-// columns go to S.U and their monomial coefficients to S.T.  Degree 0 is the
-// plain column of ones.
+// columns go to S.U and their monomial coefficients to S.T.  A column is
+// dropped when its residual norm is at most rank_tol times the largest column
+// norm, that of the ones column (sqrt n; every |xi| <= 1), the analogue of a
+// singular value cut relative to the largest one.  (Relative to the column's
+// own norm would miss an exact dependency among small columns: at the poles
+// of a fine sphere the z^2 column, of norm ~1e-4 sqrt n, keeps a rounding
+// residual of 4e-10 of its norm.)  Degree 0 is the plain column of ones.
 template <int NB>
 __device__ __forceinline__ void build_border(Shared<NB>& S, const Tid& t, int degree, double rank_tol, double xr, double yr,
                              double zr) {
@@ -618,7 +623,6 @@ __device__ __forceinline__ void build_border(Shared<NB>& S, const Tid& t, int de
     for (int l = 0; l < RMAX; ++l) {
         keep[l] = false;
         if (l < M) {
-            const double on2 = sum_rows<NB>(u[l] * u[l], S, t);
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
 #pragma unroll
@@ -631,7 +635,7 @@ __device__ __forceinline__ void build_border(Shared<NB>& S, const Tid& t, int de
                 }
             }
             const double n2 = sum_rows<NB>(u[l] * u[l], S, t);
-            if (n2 > rank_tol * rank_tol * on2 && n2 > 0.0) {
+            if (n2 > rank_tol * rank_tol * (double)n && n2 > 0.0) {
                 const double inv = 1.0 / sqrt(n2);
                 u[l] *= inv;
                 tc[l] *= inv;
