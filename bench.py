@@ -77,6 +77,29 @@ def measured_traffic():
     return rec
 
 
+FP64_PROFILE = os.path.join(ROOT, "profiles", "fp64_weights_blob_N1e6_n50.md")
+
+
+def measured_fp64():
+    """Executed FP64 rate of the learned-path weights dispatch from the committed
+    counter profile, or None when the weights source has changed since."""
+    import hashlib
+    import re
+
+    try:
+        text = open(FP64_PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"^fp64: (\{.*\})$", text, re.M)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = open(os.path.join(ROOT, "paper_1404_0812_amd", "csrc", "weights_impl.h"), "rb").read()
+    if hashlib.sha1(src).hexdigest() != rec.get("source_sha1"):
+        return None
+    return rec
+
+
 def spectral_radius(op, N, iters=300, seed=5):
     import torch
 
@@ -384,8 +407,10 @@ def main():
     w_tflops = flops / (med["weights"] / 1e3) / 1e12
     bytes_step = rk4_bytes_per_step(args.N, n, op_stats)
     rk4_gbs = bytes_step / (ms_rk4 / 1e3) / 1e9
+    f64 = measured_fp64()
     roof_w = {"bound": "alu", "achieved": w_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-              "frac": w_tflops / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_weights (FP64 VALU)"}
+              "frac": w_tflops / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_weights (FP64 VALU)",
+              "executed_fp64_tflops_counters": f64["executed_fp64_tflops"] if f64 else None}
     tr = measured_traffic()
     roof_s = {"bound": "hbm", "achieved": rk4_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": rk4_gbs / HBM_PEAK_GBS, "traffic": tr["bytes_per_launch"] if tr else None,
