@@ -333,6 +333,28 @@ def test_schnakenberg_two_species_f64_and_f32(lib, sphere_op):
     assert np.linalg.norm(g32[1] - rv) / np.linalg.norm(rv) <= 1e-5
 
 
+def test_turing_two_species_f64_and_f32(lib, sphere_op):
+    """The activator-inhibitor kinetics of Sec. 7 (eqs. turing1-2) with the
+    spots parameters of Table 1 and delta_u = 0.516 delta_v, from small noise
+    around the equilibrium (0, 0)."""
+    X, idx, W, op = sphere_op
+    rng = np.random.default_rng(12)
+    u0 = rng.uniform(-0.01, 0.01, len(X)).astype(np.float32).astype(np.float64)
+    v0 = rng.uniform(-0.01, 0.01, len(X)).astype(np.float32).astype(np.float64)
+    prm = {"alpha": 0.899, "beta": -0.91, "gamma": -0.899, "tau1": 0.02, "tau2": 0.2}
+    params = (0.899, -0.91, -0.899, 0.02, 0.2)
+    D = [0.516 * 0.01, 0.01]
+    dt, steps = 1e-3, 200
+    (ru, rv) = rk4(assemble(idx, W), [u0, v0], D, "turing", prm, dt=dt, nsteps=steps)
+    st = dev(np.stack([u0, v0]))
+    g64 = host(op.step(st, dt, steps, prec="f64", D=D, reaction="turing", params=params))
+    assert np.linalg.norm(g64[0] - ru) / np.linalg.norm(ru) <= 1e-12
+    assert np.linalg.norm(g64[1] - rv) / np.linalg.norm(rv) <= 1e-12
+    g32 = host(op.step(st, dt, steps, prec="f32", D=D, reaction="turing", params=params))
+    assert np.linalg.norm(g32[0] - ru) / np.linalg.norm(ru) <= 1e-5
+    assert np.linalg.norm(g32[1] - rv) / np.linalg.norm(rv) <= 1e-5
+
+
 def test_graph_replay_matches_eager(lib, sphere_op):
     X, idx, W, op = sphere_op
     u0 = real_sph_harm(4, 2, X)
