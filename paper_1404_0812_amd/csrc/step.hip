@@ -395,7 +395,24 @@ __device__ __forceinline__ void apply_row_halo(const RowPos& rp, const uint16_t*
         s0 = fma(wk, y[0] - yi[0], s0);
         if (S == 2) s1 = fma(wk, y[1] - yi[1], s1);
     };
-    for (int g = 0; g < G; ++g) {
+    int g = 0;
+    for (; g + 4 <= G; g += 4) {  // sixteen slots in flight
+        u4v lv[4];
+        f4v wv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            lv[q] = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(lx + 256 * (g + q)));
+            wv[q] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(wx + 256 * (g + q)));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc1(lv[q].x, wv[q].x);
+            acc1(lv[q].y, wv[q].y);
+            acc1(lv[q].z, wv[q].z);
+            acc1(lv[q].w, wv[q].w);
+        }
+    }
+    for (; g < G; ++g) {
         const u4v lv = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(lx + 256 * g));
         const f4v wv = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(wx + 256 * g));
         acc1(lv.x, wv.x);
