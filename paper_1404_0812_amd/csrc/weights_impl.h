@@ -49,12 +49,12 @@ __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp64<0x140>(v));
     return fmax(fmax(rl64(v, 0), rl64(v, 16)), fmax(rl64(v, 32), rl64(v, 48)));
 }
-// 1/q to full precision: hardware reciprocal and two Newton steps
+// 1/q for the Sturm recurrence: hardware reciprocal and one Newton step
+// (the step squares the hardware estimate's relative error; the count only
+// needs the sign of each pivot, which the recurrence gets backward-stably)
 __device__ __forceinline__ double recip(double q) {
-    double r = __builtin_amdgcn_rcp(q);
-    r = fma(r, fma(-q, r, 1.0), r);
-    r = fma(r, fma(-q, r, 1.0), r);
-    return r;
+    const double r = __builtin_amdgcn_rcp(q);
+    return fma(r, fma(-q, r, 1.0), r);
 }
 
 // ---------------------------------------------------------- radial kernels ----
