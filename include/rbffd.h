@@ -63,6 +63,7 @@ typedef struct rbffd_op_s* rbffd_op;
 #define RBFFD_ST_NONFINITE 3  /* non-finite entries in the local system */
 #define RBFFD_ST_SINGULAR 4   /* zero pivot in the tridiagonal solve */
 #define RBFFD_ST_DUPLICATE 5  /* two stencil nodes coincide */
+#define RBFFD_ST_BAD_INDEX 6  /* a stencil index outside [0, N): weights NaN, stencil skipped */
 
 /* reaction terms for rbffd_step */
 #define RBFFD_REACT_NONE 0
@@ -205,7 +206,9 @@ int rbffd_autotune_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_surface* su
  * identity), in FP64 and, for FP32 stepping, as FP32 off-diagonal weights
  * for the difference form sum_{j != i} w_ij (u_j - u_i).  *out is a HOST
  * pointer.  The operator owns device memory freed by rbffd_op_destroy.
- * Errors: N < 1, n < 2, n > 128, n > N, null idx or w.
+ * Errors: N < 1, n < 2, n > 128, n > N, null idx or w; an idx entry outside
+ * [0, N) or a perm that is not a permutation of 0..N-1 (checked on the
+ * device; the call then synchronises and returns RBFFD_E_ARG).
  */
 int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_t* idx, const double* w,
                     const int32_t* perm, rbffd_op* out);

@@ -22,7 +22,7 @@ EPS_MODES = {"fixed": 0, "given": 1, "bisect": 2, "learned": 3}
 REACTIONS = {"none": 0, "schnakenberg": 1, "turing": 2}
 PRECS = {"f64": 0, "f32": 1}
 
-ST_OK, ST_FALLBACK, ST_NO_BRACKET, ST_NONFINITE, ST_SINGULAR, ST_DUPLICATE = range(6)
+ST_OK, ST_FALLBACK, ST_NO_BRACKET, ST_NONFINITE, ST_SINGULAR, ST_DUPLICATE, ST_BAD_INDEX = range(7)
 
 
 class RbffdError(RuntimeError):

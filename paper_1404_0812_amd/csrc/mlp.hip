@@ -284,11 +284,19 @@ __global__ __launch_bounds__(64) void k_features(int64_t N, int n, const double*
     const int l = threadIdx.x;
     const int64_t s = blockIdx.x;
     if (s >= N) return;
-    const int c = idx[s * n];
+    // indices outside [0, N) read node 0 and make rho NaN (the proposal is then
+    // unusable and the weights call flags the stencil)
+    int c = idx[s * n];
+    bool bad = c < 0 || c >= N;
+    if (bad) c = 0;
     const double cx = xyz[3 * (int64_t)c], cy = xyz[3 * (int64_t)c + 1], cz = xyz[3 * (int64_t)c + 2];
     double dx = 0, dy = 0, dz = 0;
     if (l < n) {
-        const int j = idx[s * n + l];
+        int j = idx[s * n + l];
+        if (j < 0 || j >= N) {
+            bad = true;
+            j = 0;
+        }
         dx = xyz[3 * (int64_t)j] - cx;
         dy = xyz[3 * (int64_t)j + 1] - cy;
         dz = xyz[3 * (int64_t)j + 2] - cz;
@@ -296,7 +304,8 @@ __global__ __launch_bounds__(64) void k_features(int64_t N, int n, const double*
     double r2 = (dx * dx + dy * dy) + dz * dz;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
-    const double rho = sqrt(r2);
+    const bool any_bad = __ballot(bad) != 0;
+    const double rho = any_bad ? NAN : sqrt(r2);
     double nx = nrm[3 * (int64_t)c], ny = nrm[3 * (int64_t)c + 1], nz = nrm[3 * (int64_t)c + 2];
     const double nn = sqrt(nx * nx + ny * ny + nz * nz);
     nx /= nn; ny /= nn; nz /= nn;

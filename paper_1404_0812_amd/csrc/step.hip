@@ -38,28 +38,44 @@ __host__ __device__ __forceinline__ int64_t slot_pos(int k, int ns, int r) {
     return k < 4 * G ? 256 * (int64_t)(k >> 2) + 4 * r + (k & 3) : 256 * (int64_t)G + 64 * (int64_t)(k - 4 * G) + r;
 }
 
-// iperm[perm[p]] = p for one surface (perm nullable: identity)
-__global__ void k_inverse_perm(int64_t N, const int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
+// iperm[perm[p]] = p for one surface (perm nullable: identity); iperm starts
+// at -1, and a perm entry outside [0, N) sets *bad instead of being written.
+__global__ void k_inverse_perm(int64_t N, const int32_t* __restrict__ perm, int32_t* __restrict__ iperm,
+                               int* __restrict__ bad) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p < N) iperm[perm ? perm[p] : p] = (int32_t)p;
+    if (p >= N) return;
+    const int64_t v = perm ? perm[p] : p;
+    if (v >= 0 && v < N) iperm[v] = (int32_t)p;
+    else *bad = 1;
 }
 
 // Rows of one surface into the slices.  row0: first internal row of the
 // surface, col0: its first caller row; gperm: internal row -> caller row.
+// A stencil entry outside [0, N), or a row that perm does not reach, sets
+// *bad; the slot then points at the row itself with weight 0 (the operator is
+// discarded by the caller, but nothing reads out of bounds meanwhile).
 __global__ void k_build_sell(int64_t N, int n, int64_t row0, int64_t col0, const int32_t* __restrict__ idx,
                              const double* __restrict__ w, const int32_t* __restrict__ perm,
                              const int32_t* __restrict__ iperm, const OpSlice* __restrict__ slices,
                              int32_t* __restrict__ idx64, double* __restrict__ w64, int32_t* __restrict__ idx32,
-                             float* __restrict__ w32, int32_t* __restrict__ gperm) {
+                             float* __restrict__ w32, int32_t* __restrict__ gperm, int* __restrict__ bad) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const int64_t i = perm ? perm[p] : p;
+    int64_t i = perm ? perm[p] : p;
+    if (i < 0 || i >= N || iperm[p] < 0) {  // out of range, or perm misses caller row p
+        *bad = 1;
+        i = i < 0 || i >= N ? 0 : i;
+    }
     const int64_t q = row0 + p;
     const OpSlice sl = slices[q >> 6];
     const int r = (int)(q & 63);
     for (int k = 0; k < n; ++k) {
-        const int32_t j = (int32_t)(row0 + iperm[idx[i * n + k]]);
-        const double wk = w[i * n + k];
+        const int32_t c = idx[i * n + k];
+        const int32_t ip = (c >= 0 && c < N) ? iperm[c] : -1;
+        const bool ok = ip >= 0;
+        if (!ok) *bad = 1;
+        const int32_t j = (int32_t)(row0 + (ok ? ip : p));
+        const double wk = ok ? w[i * n + k] : 0.0;
         const int64_t q64 = sl.off64 + slot_pos(k, n, r);
         idx64[q64] = j;
         w64[q64] = wk;
@@ -604,22 +620,28 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
               hipMalloc(&op->halo, std::max<size_t>(1, sl.size()) * OP_HALO_MAX * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&op->perm, std::max<int64_t>(1, P) * sizeof(int32_t)) == hipSuccess;
     int32_t* iperm = nullptr;
+    int* bad = nullptr;
     ok = ok && hipMalloc(&iperm, std::max<int64_t>(1, maxN) * sizeof(int32_t)) == hipSuccess;
+    ok = ok && hipMalloc(&bad, sizeof(int)) == hipSuccess;
     if (!ok) {
         rbffd_op_destroy(op);
         if (iperm) (void)hipFree(iperm);
+        if (bad) (void)hipFree(bad);
         return set_error(ctx, RBFFD_E_NOMEM, "operator allocation failed");
     }
     hipStream_t st = ctx->stream;
     hipError_t e = hipMemcpyAsync(op->slices, sl.data(), sl.size() * sizeof(OpSlice), hipMemcpyHostToDevice, st);
     // padding rows: perm -1; their slots are never read (rows >= OpSlice::rows are skipped)
     if (e == hipSuccess) e = hipMemsetAsync(op->perm, 0xff, (size_t)P * sizeof(int32_t), st);
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), st);
     for (int s = 0; s < nsurf && e == hipSuccess; ++s) {
         const int64_t Ns = surf[s].N;
         const dim3 g((unsigned)((Ns + BLK - 1) / BLK)), b(BLK);
-        hipLaunchKernelGGL(k_inverse_perm, g, b, 0, st, Ns, surf[s].perm, iperm);
+        e = hipMemsetAsync(iperm, 0xff, (size_t)Ns * sizeof(int32_t), st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_inverse_perm, g, b, 0, st, Ns, surf[s].perm, iperm, bad);
         hipLaunchKernelGGL(k_build_sell, g, b, 0, st, Ns, surf[s].n, row0[s], col0[s], surf[s].idx, surf[s].w,
-                           surf[s].perm, iperm, op->slices, op->idx64, op->w64, op->idx32, op->w32, op->perm);
+                           surf[s].perm, iperm, op->slices, op->idx64, op->w64, op->idx32, op->w32, op->perm, bad);
         e = hipGetLastError();
     }
     if (e == hipSuccess && !sl.empty()) {
@@ -630,10 +652,17 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
     // the slice table comes from pageable host memory and iperm is reused per surface: wait here
     const hipError_t e2 = hipStreamSynchronize(st);
     if (e == hipSuccess) e = e2;
+    int bad_h = 0;
+    if (e == hipSuccess) e = hipMemcpy(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost);
     (void)hipFree(iperm);
+    (void)hipFree(bad);
     if (e != hipSuccess) {
         rbffd_op_destroy(op);
         return set_error(ctx, RBFFD_E_HIP, "operator build failed: %s", hipGetErrorString(e));
+    }
+    if (bad_h) {
+        rbffd_op_destroy(op);
+        return set_error(ctx, RBFFD_E_ARG, "stencil or perm entry outside [0, N) (or perm not a permutation)");
     }
     *out = op;
     return RBFFD_OK;

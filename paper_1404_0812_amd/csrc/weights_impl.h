@@ -677,8 +677,11 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
     const int c = t.c;
     // ---- gather the stencil (thread's column node; rb == 0 threads fill LDS)
     double px = 0, py = 0, pz = 0, nx = 0, ny = 0, nz = 0;
+    bool bad = false;  // stencil index outside [0, N): read node 0 instead, flag the stencil
     if (c < n) {
-        const int64_t node = J.idx[s * n + c];
+        int64_t node = J.idx[s * n + c];
+        bad = node < 0 || node >= J.N;
+        if (bad) node = 0;
         px = J.xyz[3 * node];
         py = J.xyz[3 * node + 1];
         pz = J.xyz[3 * node + 2];
@@ -703,7 +706,20 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
     // ---- stencil radius, scaled offsets of the thread's column node and row node
     const double dx0 = px - S.x[0], dy0 = py - S.y[0], dz0 = pz - S.z[0];
     const double r20 = c < n ? (dx0 * dx0 + dy0 * dy0) + dz0 * dz0 : 0.0;
-    const double dupf = max_cols<NB>((c > 0 && c < n && r20 == 0.0) ? 1.0 : 0.0, S, t);
+    // 2: an index out of range somewhere in the stencil; 1: two nodes coincide
+    const double flagf = max_cols<NB>(bad ? 2.0 : ((c > 0 && c < n && r20 == 0.0) ? 1.0 : 0.0), S, t);
+    if (flagf >= 2.0) {
+        if (t.tid == 0) {
+            if (J.eps) J.eps[s] = NAN;
+            if (J.kappa) J.kappa[s] = NAN;
+            if (J.nevals) J.nevals[s] = 0;
+            if (J.status) J.status[s] = RBFFD_ST_BAD_INDEX;
+        }
+        if (!J.kappa_only && c < n && t.rb == 0) J.w[s * n + c] = NAN;
+        bsync<NB>();
+        return;
+    }
+    const double dupf = flagf;
     const double rho = sqrt(max_cols<NB>(r20, S, t));
     const double irho = 1.0 / rho;
     const double xi = dx0 / rho, yi = dy0 / rho, zi = dz0 / rho;

@@ -383,3 +383,27 @@ def test_weights_against_60_digit_truth(lib, sphere):
         eg = np.linalg.norm(wg[i] - wt) / nt
         eo = np.linalg.norm(wo - wt) / nt
         assert eg <= max(2 * eo, 0.1 * k * U64) + 1e-12, (i, eg / (k * U64), eo / (k * U64))
+
+
+def test_out_of_range_indices_are_flagged(lib, sphere):
+    """Stencil entries outside [0, N) are caught on the device: the weights
+    call marks that stencil (status 6, NaN weights) and leaves the others
+    alone; the operator build refuses the stencils and a non-permutation."""
+    X, nrm, idx = sphere
+    bad = idx.copy()
+    bad[7, 3] = len(X) + 5
+    bad[9, 0] = -1
+    ref = lib.build_weights(dev(X), dev(nrm), 31, idx=dev(idx, torch.int32), eps_mode="fixed", eps=4.0)
+    got = lib.build_weights(dev(X), dev(nrm), 31, idx=dev(bad, torch.int32), eps_mode="fixed", eps=4.0)
+    st = host(got.status)
+    assert st[7] == lib.ST_BAD_INDEX and st[9] == lib.ST_BAD_INDEX
+    w = host(got.w)
+    assert np.all(np.isnan(w[7])) and np.all(np.isnan(w[9]))
+    keep = np.setdiff1d(np.arange(len(X)), [7, 9])
+    assert np.array_equal(w[keep], host(ref.w)[keep]) and np.all(st[keep] == 0)
+    with pytest.raises(lib.RbffdError):
+        lib.Operator(dev(bad, torch.int32), ref.w)
+    perm = np.arange(len(X), dtype=np.int32)
+    perm[5] = 6  # 5 is never reached
+    with pytest.raises(lib.RbffdError):
+        lib.Operator(dev(idx, torch.int32), ref.w, perm=dev(perm, torch.int32))
