@@ -178,6 +178,9 @@ typedef struct {
 /* surf: HOST array of nsurf descriptors (device pointers inside).  tuning:
  * HOST array of RBFFD_BUCKETS schedules, or NULL for the built-in default
  * (16 stencils per item in bucket 0, 2 in bucket 1, 2 groups per CU, order 0).
+ * The call first drains the context's stream (the host waits for work
+ * enqueued earlier) and then uploads the work list; the weights themselves
+ * are enqueued asynchronously as usual.
  * Errors: as rbffd_build_weights for any surface (the message names it);
  * nsurf < 0; a schedule out of range. */
 int rbffd_build_weights_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_surface* surf,

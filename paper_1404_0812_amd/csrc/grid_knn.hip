@@ -21,6 +21,9 @@
 
 namespace {
 
+#ifndef KNN_CELL_SCALE
+#define KNN_CELL_SCALE 1.0  // cell edge relative to the expected stencil radius
+#endif
 constexpr int KNN_CAP = 1024;  // candidate buffer per query (entries)
 constexpr int MAX_BITS = 9;    // Morton bits per axis (2^27 cells at most)
 
@@ -367,7 +370,7 @@ int knn_internal(rbffd_ctx ctx, int64_t N, const double* xyz, int32_t n, int32_t
     // surface-area proxy: half the bounding-box surface; cell ~ expected stencil radius
     double area = ext[0] * ext[1] + ext[1] * ext[2] + ext[0] * ext[2];
     if (area <= 0) area = emax * emax;
-    double h = std::sqrt(std::max(n, 8) * area / (M_PI * (double)N));
+    double h = KNN_CELL_SCALE * std::sqrt(std::max(n, 8) * area / (M_PI * (double)N));
     if (!(h > 0)) h = emax;
     h = std::max(h, emax / (double)(1 << MAX_BITS));
     Grid G;
