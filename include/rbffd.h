@@ -42,7 +42,7 @@ typedef struct rbffd_op_s* rbffd_op;
 #define RBFFD_E_ARG (-1)      /* invalid argument (sizes, enum values, null pointer) */
 #define RBFFD_E_HIP (-2)      /* a HIP runtime call failed */
 #define RBFFD_E_NOMEM (-3)    /* device allocation of library scratch failed */
-#define RBFFD_E_UNSUPPORTED (-4) /* valid request outside what this build implements */
+#define RBFFD_E_UNSUPPORTED (-4) /* valid request outside what this library implements */
 
 /* radial kernels (Sec. 2) */
 #define RBFFD_KERNEL_MQ 0  /* sqrt(1 + (eps r)^2) */

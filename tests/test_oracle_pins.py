@@ -284,7 +284,7 @@ def test_rk4_one_step_is_taylor_quartic():
 
 
 def test_heat_decay_on_sphere_against_exact(sphere2500):
-    """configs[0]-type run: u0 = Y_6^3 + 0.1 Y_2^1 decays as exp(-l(l+1)t).
+    """The N = 2500 unit-sphere heat run: u0 = Y_6^3 + 0.1 Y_2^1 decays as exp(-l(l+1)t).
     The error is discretisation error (measured 1.98e-3 at t = 0.1)."""
     X, nrm, idx = sphere2500
     L = assemble(idx, build_weights(X, nrm, idx, 2.0))
