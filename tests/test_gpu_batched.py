@@ -208,3 +208,31 @@ def test_batched_edge_surfaces(lib):
     k = host(got[2].kappa)[rows]
     err = np.linalg.norm(wg - wo, axis=1) / np.linalg.norm(wo, axis=1)
     assert np.all(err <= np.maximum(1e-9, 0.5 * k * 2.0 ** -53)), err
+
+
+def test_autotune_cache_file_read_by_a_new_process(lib, batch, tmp_path):
+    """A second process reads the schedule from the JSON file written by the
+    first (no timing: the cached per-stencil time comes back unchanged)."""
+    import subprocess
+    import sys
+
+    surfs, meta = batch
+    path = str(tmp_path / "tune2.json")
+    t1 = lib.autotune_batched(surfs[:3], cache_path=path, retune=True, eps_mode="bisect", kappa_target=1e12)
+    np.savez(str(tmp_path / "surf.npz"), **{f"X{i}": m["X"] for i, m in enumerate(meta[:3])},
+             **{f"N{i}": m["nrm"] for i, m in enumerate(meta[:3])}, n=np.array([m["n"] for m in meta[:3]]))
+    code = f"""
+import json, sys, numpy as np, torch
+sys.path.insert(0, {repr(str(__import__('pathlib').Path(__file__).resolve().parents[1]))})
+import paper_1404_0812_amd as rb
+z = np.load({repr(str(tmp_path / 'surf.npz'))})
+surfs = [(torch.as_tensor(z[f'X{{i}}']).cuda(), torch.as_tensor(z[f'N{{i}}']).cuda(), int(z['n'][i])) for i in range(3)]
+t = rb.autotune_batched(surfs, cache_path={repr(path)}, eps_mode='bisect', kappa_target=1e12)
+print(json.dumps(t))
+"""
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    t2 = json.loads(out.stdout.strip().splitlines()[-1])
+    for a, b in zip(t1, t2):
+        assert (a["stencils_per_item"], a["groups_per_cu"], a["order"]) == (b["stencils_per_item"], b["groups_per_cu"], b["order"])
+        assert abs(a["us_per_stencil"] - b["us_per_stencil"]) <= 1e-5 * max(1.0, a["us_per_stencil"])
