@@ -242,6 +242,47 @@ __device__ __forceinline__ int next_pow2(int v) {
     return p;
 }
 
+// Drop candidates that cannot be among the `need` nearest before the sort.
+// Lane l's minimum over entries l, l + 64, ... is a distance attained by a
+// distinct candidate per lane, so the need-th smallest of the 64 lane minima
+// (need <= 64) bounds the need-th smallest distance from above; entries with
+// a larger distance are discarded (ties with the bound are kept) and the rest
+// compacted to the front.  Returns the new count.
+__device__ int prefilter(double* cd, int* cid, int cnt, int need) {
+    const int lane = threadIdx.x;
+    double lm = INFINITY;
+    for (int t = lane; t < cnt; t += 64) lm = fmin(lm, cd[t]);
+    int rank = 0;  // position of this lane's minimum among all 64 (ties by lane)
+    for (int o = 0; o < 64; ++o) {
+        const double v = __shfl(lm, o, 64);
+        rank += (v < lm || (v == lm && o < lane)) ? 1 : 0;
+    }
+    const uint64_t who = __ballot(rank == need - 1);
+    const double bound = __shfl(lm, __ffsll((unsigned long long)who) - 1, 64);
+    int kept = 0;
+    for (int b = 0; b < cnt; b += 64) {
+        const int t = b + lane;
+        double d = INFINITY;
+        int id = 0;
+        bool keep = false;
+        if (t < cnt) {
+            d = cd[t];
+            id = cid[t];
+            keep = d <= bound;
+        }
+        const uint64_t m = __ballot(keep);
+        __syncthreads();  // every lane has read its entry of this block
+        if (keep) {
+            const int pos = kept + __popcll(m & ((1ull << lane) - 1ull));  // pos <= t: earlier blocks are done
+            cd[pos] = d;
+            cid[pos] = id;
+        }
+        kept += __popcll(m);
+        __syncthreads();
+    }
+    return kept;
+}
+
 // One 64-lane workgroup per query position p (spatial order).
 __global__ __launch_bounds__(64) void k_knn(int64_t N, int n, Grid G, const double* __restrict__ xs,
                                              const double* __restrict__ ys, const double* __restrict__ zs,
@@ -321,6 +362,7 @@ __global__ __launch_bounds__(64) void k_knn(int64_t N, int n, Grid G, const doub
         bool covers = (cx - R <= 0) && (cy - R <= 0) && (cz - R <= 0) && (cx + R >= G.g[0] - 1) &&
                       (cy + R >= G.g[1] - 1) && (cz + R >= G.g[2] - 1);
         if (cnt >= need) {
+            if (need <= 64 && cnt > 128) cnt = prefilter(cd, cid, cnt, need);
             int S = next_pow2(cnt);
             for (int t = cnt + lane; t < S; t += 64) {
                 cd[t] = INFINITY;
