@@ -243,22 +243,44 @@ __device__ __forceinline__ int next_pow2(int v) {
 }
 
 // Drop candidates that cannot be among the `need` nearest before the sort.
-// Lane l's minimum over entries l, l + 64, ... is a distance attained by a
-// distinct candidate per lane, so the need-th smallest of the 64 lane minima
-// (need <= 64) bounds the need-th smallest distance from above; entries with
-// a larger distance are discarded (ties with the bound are kept) and the rest
-// compacted to the front.  Returns the new count.
+// Entry t belongs to group (t / 64) % NG of lane t % 64; each of the 64 NG
+// groups' minimum is a distance attained by a distinct candidate, so the
+// need-th smallest of those minima (need <= 64 NG) bounds the need-th smallest
+// distance from above.  Entries with a larger distance are discarded (ties
+// with the bound are kept) and the rest compacted to the front.  Returns the
+// new count.
+template <int NG>
 __device__ int prefilter(double* cd, int* cid, int cnt, int need) {
     const int lane = threadIdx.x;
-    double lm = INFINITY;
-    for (int t = lane; t < cnt; t += 64) lm = fmin(lm, cd[t]);
-    int rank = 0;  // position of this lane's minimum among all 64 (ties by lane)
-    for (int o = 0; o < 64; ++o) {
-        const double v = __shfl(lm, o, 64);
-        rank += (v < lm || (v == lm && o < lane)) ? 1 : 0;
+    double lm[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) lm[g] = INFINITY;
+    for (int b = 0; b < cnt; b += 64 * NG) {
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const int t = b + 64 * g + lane;
+            if (t < cnt) lm[g] = fmin(lm[g], cd[t]);
+        }
     }
-    const uint64_t who = __ballot(rank == need - 1);
-    const double bound = __shfl(lm, __ffsll((unsigned long long)who) - 1, 64);
+    // rank of each group minimum among all 64 NG (ties by (group, lane))
+    int rank[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) rank[g] = 0;
+    for (int o = 0; o < 64; ++o) {
+#pragma unroll
+        for (int h = 0; h < NG; ++h) {
+            const double v = __shfl(lm[h], o, 64);
+#pragma unroll
+            for (int g = 0; g < NG; ++g)
+                rank[g] += (v < lm[g] || (v == lm[g] && (h < g || (h == g && o < lane)))) ? 1 : 0;
+        }
+    }
+    double bound = INFINITY;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const uint64_t who = __ballot(rank[g] == need - 1);
+        if (who) bound = __shfl(lm[g], __ffsll((unsigned long long)who) - 1, 64);
+    }
     int kept = 0;
     for (int b = 0; b < cnt; b += 64) {
         const int t = b + lane;
@@ -362,7 +384,8 @@ __global__ __launch_bounds__(64) void k_knn(int64_t N, int n, Grid G, const doub
         bool covers = (cx - R <= 0) && (cy - R <= 0) && (cz - R <= 0) && (cx + R >= G.g[0] - 1) &&
                       (cy + R >= G.g[1] - 1) && (cz + R >= G.g[2] - 1);
         if (cnt >= need) {
-            if (need <= 64 && cnt > 128) cnt = prefilter(cd, cid, cnt, need);
+            if (need <= 64 && cnt > 128) cnt = prefilter<1>(cd, cid, cnt, need);
+            else if (need <= 128 && cnt > 256) cnt = prefilter<2>(cd, cid, cnt, need);
             int S = next_pow2(cnt);
             for (int t = cnt + lane; t < S; t += 64) {
                 cd[t] = INFINITY;

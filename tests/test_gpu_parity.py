@@ -55,10 +55,18 @@ def oracle_kappas(X, idx, eps, rows, **kw):
 
 # ------------------------------------------------------------------ kNN ----
 
-@pytest.mark.parametrize("case", ["sphere2500_n31", "torus_n50", "blob_n50", "lattice_ties", "all_nodes"])
+@pytest.mark.parametrize("case", ["sphere2500_n31", "torus_n50", "blob_n50", "lattice_ties", "all_nodes",
+                                  "ellipsoid_n70", "blob_n101", "sphere_n128"])
 def test_knn_exact(lib, case):
     if case == "sphere2500_n31":
         X, _ = fibonacci_sphere(2500); n = 31
+    elif case == "ellipsoid_n70":
+        from synth import ellipsoid
+        X, _ = ellipsoid(4000, 1.5, 1.0, 0.6); n = 70
+    elif case == "blob_n101":
+        X, _ = blob(6000, oversample=2.0); n = 101
+    elif case == "sphere_n128":
+        X, _ = fibonacci_sphere(3000); n = 128
     elif case == "torus_n50":
         X, _ = jittered_torus(40, 120); n = 50
     elif case == "blob_n50":
