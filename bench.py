@@ -45,11 +45,12 @@ def rk4_bytes_per_step(N, n, stats=None, species=2):
     entries: 2-byte positions in the slice's halo list for rows of slices whose
     halo is staged in LDS (plus 4 bytes per halo-list entry), 4-byte row
     indices for the others; and per row the species values: stage inputs
-    24/40/40/32 B for two FP32 species (stage input once, own state,
-    accumulator, next input).  stats = Operator.stats()."""
+    24/40/40/48 B for two FP32 species (stage input once, own state,
+    accumulator, next input; the last stage reads and writes the compensation
+    term of the state update).  stats = Operator.stats()."""
     hr, he = (stats[2], stats[3]) if stats else (0, 0)
     mat = hr * (n - 1) * (4 + 2) + (N - hr) * (n - 1) * (4 + 4) + he * 4
-    vec = N * species * 4 * (3 + 5 + 5 + 4)
+    vec = N * species * 4 * (3 + 5 + 5 + 6)
     return 4 * mat + vec
 
 
@@ -234,7 +235,7 @@ def batched_section(rb, ctx, kappa_T=1e12, count=64, diffusion_steps=1000, seed=
     rows_n = [(int(s[0].shape[0]), s[2]) for s in surfs]
     slots = sum(N_ * (n_ - 1) for N_, n_ in rows_n)
     halo_frac = hr / total
-    step_bytes = 4 * (slots * 4 + slots * (2 * halo_frac + 4 * (1 - halo_frac)) + he * 4) + total * 4 * (3 + 5 + 5 + 4)
+    step_bytes = 4 * (slots * 4 + slots * (2 * halo_frac + 4 * (1 - halo_frac)) + he * 4) + total * 4 * (3 + 5 + 5 + 6)
     ns = {}
     for _, _, n in surfs:
         ns[str(n)] = ns.get(str(n), 0) + 1
@@ -396,6 +397,12 @@ def main():
             status = res.status.cpu().numpy()
             kap = res.kappa.cpu().numpy()
             fin = out.cpu().numpy()
+            # FP32 state against an FP64 run of the same steps (untimed); FP64 on
+            # this path matches the oracle to 1e-12 in the tests
+            ref64 = op.step(state0, dt_rk4, args.rk4_steps, prec="f64", D=DIFF, reaction="schnakenberg",
+                            params=SCHNAK, graph_steps=100).cpu().numpy()
+            fp32_vs_fp64 = float(np.linalg.norm(fin - ref64) / np.linalg.norm(ref64))
+            print(f"[bench] FP32 vs FP64 state after {args.rk4_steps} steps: {fp32_vs_fp64:.3e}", flush=True)
         del op
 
     med = {k: float(np.median([r[k] for r in rows])) for k in rows[0]}
@@ -514,6 +521,7 @@ def main():
                           {str(k): int(v) for k, v in zip(*np.unique(status, return_counts=True))},
                           "median_log10_kappa": float(np.median(np.log10(kap)))},
         "state_finite": bool(np.isfinite(fin).all()),
+        "fp32_vs_fp64_rel_l2": fp32_vs_fp64,
         "training": train_info,
         "learned_vs_bisection": compare,
         "batched": batched,

@@ -463,7 +463,8 @@ __device__ __forceinline__ void laplacian_row(const StageArgs& a, const RowPos& 
 }
 
 // RK4 stage `ST` (0..3).  Y: stage input; U: state at the start of the step;
-// ACC: accumulator; YN: next stage input (stages 0-2) -- stage 3 updates U.
+// ACC: accumulator; YN: next stage input (stages 0-2) -- stage 3 updates U
+// (FP32: YN is then the compensation term of the update).
 template <typename T, int S, int R, int ST>
 __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* __restrict__ idx,
                                                    const T* __restrict__ w, const T* __restrict__ Y,
@@ -502,9 +503,26 @@ __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* _
     } else {
         vload<T, S>(U, p, u);
         vload<T, S>(ACC, p, c);
-        o[0] = u[0] + dt / (T)6 * (c[0] + k[0]);
-        o[1] = u[1] + dt / (T)6 * (c[1] + k[1]);
-        vstore<T, S>(U, p, o);
+        if constexpr (sizeof(T) == 4) {
+            // FP32 state: compensated (Kahan) update, the running rounding error
+            // kept in YN; over 1e4 steps of increments ~1e-4 of the state the
+            // plain update drifts by several 1e-5 against FP64
+            T e[2];
+            vload<T, S>(YN, p, e);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const T d = dt / (T)6 * (c[q] + k[q]) - e[q];
+                const T t = u[q] + d;
+                e[q] = (t - u[q]) - d;
+                o[q] = t;
+            }
+            vstore<T, S>(U, p, o);
+            vstore<T, S>(YN, p, e);
+        } else {
+            o[0] = u[0] + dt / (T)6 * (c[0] + k[0]);
+            o[1] = u[1] + dt / (T)6 * (c[1] + k[1]);
+            vstore<T, S>(U, p, o);
+        }
     }
 }
 
@@ -525,26 +543,28 @@ __global__ __launch_bounds__(BLK) void k_apply(StageArgs a, const int32_t* __res
 inline dim3 stage_grid(int64_t nslices) { return dim3((unsigned)((nslices + BLK / 64 - 1) / (BLK / 64))); }
 
 template <typename T, int S, int R>
-void enqueue_step(hipStream_t st, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC, T* Y1, T* Y2) {
+void enqueue_step(hipStream_t st, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC, T* Y1, T* Y2,
+                  T* COMP) {
     const dim3 g = stage_grid(a.nslices), b(BLK);
     hipLaunchKernelGGL((k_rk4_stage<T, S, R, 0>), g, b, 0, st, a, idx, w, U, U, ACC, Y1);
     hipLaunchKernelGGL((k_rk4_stage<T, S, R, 1>), g, b, 0, st, a, idx, w, Y1, U, ACC, Y2);
     hipLaunchKernelGGL((k_rk4_stage<T, S, R, 2>), g, b, 0, st, a, idx, w, Y2, U, ACC, Y1);
-    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 3>), g, b, 0, st, a, idx, w, Y1, U, ACC, nullptr);
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 3>), g, b, 0, st, a, idx, w, Y1, U, ACC, COMP);
 }
 
 template <typename T>
 void enqueue_steps_t(hipStream_t st, int S, int R, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC,
+                     T* COMP,
                      T* Y1, T* Y2, int64_t steps) {
     for (int64_t i = 0; i < steps; ++i) {
         if (S == 1) {
-            enqueue_step<T, 1, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2);
+            enqueue_step<T, 1, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
         } else if (R == RBFFD_REACT_SCHNAKENBERG) {
-            enqueue_step<T, 2, RBFFD_REACT_SCHNAKENBERG>(st, a, idx, w, U, ACC, Y1, Y2);
+            enqueue_step<T, 2, RBFFD_REACT_SCHNAKENBERG>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
         } else if (R == RBFFD_REACT_TURING) {
-            enqueue_step<T, 2, RBFFD_REACT_TURING>(st, a, idx, w, U, ACC, Y1, Y2);
+            enqueue_step<T, 2, RBFFD_REACT_TURING>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
         } else {
-            enqueue_step<T, 2, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2);
+            enqueue_step<T, 2, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
         }
     }
 }
@@ -811,21 +831,25 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     void* ACC = base + 2 * P * esz;
     void* Y1 = base + 4 * P * esz;
     void* Y2 = base + 6 * P * esz;
+    // FP32: compensation of the state update (inside the FP64-sized work area)
+    void* COMP = prec == RBFFD_F64 ? nullptr : (void*)(base + 8 * P * esz);
     const int32_t* idx = prec == RBFFD_F64 ? op->idx64 : op->idx32;
     const void* w = prec == RBFFD_F64 ? (const void*)op->w64 : (const void*)op->w32;
-    if (prec == RBFFD_F64)
+    if (prec == RBFFD_F64) {
         hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, nspecies, state, op->perm, (double*)U);
-    else
+    } else {
         hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, P, N, nspecies, state, op->perm, (float*)U);
+        HIP_TRY(ctx, hipMemsetAsync(COMP, 0, 2 * (size_t)P * sizeof(float), st));  // outside any captured graph
+    }
     HIP_TRY(ctx, hipGetLastError());
 
     auto enqueue = [&](hipStream_t s, int64_t steps) {
         if (prec == RBFFD_F64)
             enqueue_steps_t<double>(s, nspecies, reaction, a, idx, (const double*)w, (double*)U, (double*)ACC,
-                                    (double*)Y1, (double*)Y2, steps);
+                                    nullptr, (double*)Y1, (double*)Y2, steps);
         else
             enqueue_steps_t<float>(s, nspecies, reaction, a, idx, (const float*)w, (float*)U, (float*)ACC,
-                                   (float*)Y1, (float*)Y2, steps);
+                                   (float*)COMP, (float*)Y1, (float*)Y2, steps);
     };
     const int64_t reps = nsteps / G;
     const int64_t rest = nsteps % G;
