@@ -315,9 +315,11 @@ struct Spectrum {
     double pivmin;
 };
 
-// Largest |lambda| of T to ~33^-rounds of the Gershgorin width.
+// Largest |lambda| of T to ~33^-rounds of the Gershgorin width; with rel > 0
+// the multisection stops as soon as both brackets are within 2 rel of the
+// current estimate of max |lambda| (midpoint error <= rel relative).
 template <int NB>
-__device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, int rounds) {
+__device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, int rounds, double rel = 0.0) {
     const int m = S.m;
     Spectrum sp;
     double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
@@ -342,6 +344,10 @@ __device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, 
     double lo1 = gl, hi1 = gu, lo2 = gl, hi2 = gu;
     const int g = lane >> 5, tt = lane & 31;
     for (int rd = 0; rd < rounds; ++rd) {
+        if (rel > 0.0) {  // uniform: the brackets are wave-uniform
+            const double est = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
+            if (fmax(hi1 - lo1, hi2 - lo2) <= 2.0 * rel * est) break;
+        }
         const double lo = g ? lo2 : lo1, hi = g ? hi2 : hi1;
         const double sig = lo + (hi - lo) * (double)(tt + 1) / 33.0;
         const int kidx = g ? m : 1;
@@ -375,16 +381,34 @@ __device__ __forceinline__ void small_counts(const Shared<NB>& S, int lane, cons
     cb = c3 - c2;
 }
 
-// Smallest |lambda| (geometric multisection on both sides of zero).
+// Band test and inertia in one pass: #eigenvalues with |lambda| < tau_a and
+// with |lambda| < tau_b (lanes 0-3), and nu = #eigenvalues below zero (lane 4).
 template <int NB>
-__device__ __forceinline__ double spectrum_min_abs(const Shared<NB>& S, int lane, const Spectrum& sp, int rounds) {
+__device__ __forceinline__ void band_counts(const Shared<NB>& S, int lane, const Spectrum& sp, double tau_a,
+                                            double tau_b, int& ca, int& cb, int& nu) {
     const int m = S.m;
-    const int nu = sturm<NB>(S, m, 0.0, sp.pivmin);  // eigenvalues below zero (uniform)
-    const double H = sp.amax * (1.0 + 1e-12) + sp.pivmin;
-    const double L = sp.amax * 1e-30 + sp.pivmin;
+    double sig = 0.0;
+    if (lane == 0) sig = -tau_a;
+    if (lane == 1) sig = tau_a;
+    if (lane == 2) sig = -tau_b;
+    if (lane == 3) sig = tau_b;
+    const int c = lane < 5 ? sturm<NB>(S, m, sig, sp.pivmin) : 0;
+    const int c0 = __shfl(c, 0, 64), c1 = __shfl(c, 1, 64), c2 = __shfl(c, 2, 64), c3 = __shfl(c, 3, 64);
+    ca = c1 - c0;
+    cb = c3 - c2;
+    nu = __shfl(c, 4, 64);
+}
+
+// Smallest |lambda| (geometric multisection on both sides of zero) within
+// [L, H]; nu = #eigenvalues below zero.  Rounds continue until the log
+// brackets are 2 rel wide (midpoint error <= rel relative), at most `rounds`.
+template <int NB>
+__device__ __forceinline__ double spectrum_min_abs_in(const Shared<NB>& S, int lane, const Spectrum& sp, int nu,
+                                                      double L, double H, int rounds, double rel) {
+    const int m = S.m;
     double lp = log(L), hp = log(H), ln_ = log(L), hn = log(H);
     const int g = lane >> 5, tt = lane & 31;
-    for (int rd = 0; rd < rounds; ++rd) {
+    for (int rd = 0; rd < rounds && (hp - lp) > 2.0 * rel; ++rd) {
         const double lo = g ? ln_ : lp, hi = g ? hn : hp;
         const double sig = exp(lo + (hi - lo) * (double)(tt + 1) / 33.0);
         bool above;  // target magnitude lies above sig
@@ -403,6 +427,14 @@ __device__ __forceinline__ double spectrum_min_abs(const Shared<NB>& S, int lane
     const double pos = nu < m ? exp(0.5 * (lp + hp)) : INFINITY;
     const double neg = nu > 0 ? exp(0.5 * (ln_ + hn)) : INFINITY;
     return fmin(pos, neg);
+}
+
+// Smallest |lambda| with no prior bracket: [1e-30, 1] x max |lambda|, 7 rounds.
+template <int NB>
+__device__ __forceinline__ double spectrum_min_abs(const Shared<NB>& S, int lane, const Spectrum& sp) {
+    const int nu = sturm<NB>(S, S.m, 0.0, sp.pivmin);  // eigenvalues below zero (uniform)
+    return spectrum_min_abs_in<NB>(S, lane, sp, nu, sp.amax * 1e-30 + sp.pivmin,
+                                   sp.amax * (1.0 + 1e-12) + sp.pivmin, 7, 0.0);
 }
 
 // ------------------------------------------------------- tridiagonal solve ----
@@ -653,10 +685,10 @@ __device__ __forceinline__ void build_border(Shared<NB>& S, const Tid& t, int de
 // ------------------------------------------------------ kappa evaluations ----
 template <int K, int NB>
 __device__ __forceinline__ Spectrum eval_spectrum(double (&a)[64], Shared<NB>& S, const Tid& t, double eps,
-                                                  int rounds) {
+                                                  int rounds, double rel = 0.0) {
     build_matrix<K, NB>(a, S, t, eps * eps);
     tridiagonalise<NB>(a, S, t);
-    return spectrum_max<NB>(S, t.lane, rounds);
+    return spectrum_max<NB>(S, t.lane, rounds, rel);
 }
 
 // kappa > target ?  (non-finite counts as above, like an infinite kappa)
@@ -741,6 +773,7 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
 
     // ---- shape parameter
     bool have_final = false;  // registers / S hold the tridiagonal form at eps
+    double amin_known = 0.0;  // min |lambda| if already found
     Spectrum sp;
     if (o.mode == RBFFD_EPS_FIXED) {
         eps = o.eps_fixed;
@@ -751,14 +784,18 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
         if (o.mode == RBFFD_EPS_LEARNED) {
             eps = J.eps_in[s];
             if (isfinite(eps) && eps > 0.0) {
-                sp = eval_spectrum<K, NB>(a, S, t, eps, 8);  // also the reported kappa if kept
+                // max |lambda| to band_rel: also the reported kappa's if kept
+                sp = eval_spectrum<K, NB>(a, S, t, eps, 8, o.band_rel);
                 ++evals;
                 if (sp.finite && sp.amax > 0.0) {
-                    int c_lo, c_hi;  // |lambda| below amax/band_lo and below amax/band_hi
-                    small_counts<NB>(S, t.lane, sp, sp.amax / o.band_lo, sp.amax / o.band_hi, c_lo, c_hi);
+                    int c_lo, c_hi, nu;  // |lambda| below amax/band_lo and below amax/band_hi
+                    const double tau_lo = sp.amax / o.band_lo, tau_hi = sp.amax / o.band_hi;
+                    band_counts<NB>(S, t.lane, sp, tau_lo, tau_hi, c_lo, c_hi, nu);
                     if (c_lo > 0 && c_hi == 0) {  // band_lo < kappa <= band_hi
                         need_bisect = false;
                         have_final = true;
+                        // min |lambda| lies in [tau_hi, tau_lo)
+                        amin_known = spectrum_min_abs_in<NB>(S, t.lane, sp, nu, tau_hi, tau_lo, 7, o.band_rel);
                     }
                 }
             }
@@ -816,7 +853,7 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
     // ---- kappa_2 at the final eps
     double kappa = NAN;
     if (sp.finite && sp.amax > 0.0) {
-        const double amin = spectrum_min_abs<NB>(S, t.lane, sp, 7);
+        const double amin = amin_known > 0.0 ? amin_known : spectrum_min_abs<NB>(S, t.lane, sp);
         kappa = sp.amax / amin;
     } else if (status == RBFFD_ST_OK) {
         status = RBFFD_ST_NONFINITE;

@@ -11,6 +11,7 @@ struct WOpts {
     int n, kernel, degree, mode;
     double eps_fixed, kappa_target, eps_tol, br_lo, br_hi, band_lo, band_hi, rank_tol;
     int band_stop, max_expand;
+    double band_rel;  // multisection precision of a kappa found inside the band
 };
 
 // One stencil set: inputs, options and outputs (device pointers).
