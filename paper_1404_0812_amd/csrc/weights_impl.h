@@ -17,9 +17,9 @@ template <int NB>
 constexpr int chunk_rows() { return NB == 1 ? 8 : 16; }
 
 // ------------------------------------------------------------ reductions ----
-// Wavefront reductions with DPP (within rows of 16 lanes) and readlane (across
-// the four rows).  Every lane must be active; the result is the same, bit for
-// bit, in every lane.
+// Wavefront reductions with DPP (within rows of 16 lanes) and the row swaps
+// (across the four rows).  Every lane must be active; the result is the same,
+// bit for bit, in every lane.
 template <int CTRL>
 __device__ __forceinline__ double dpp64(double v) {
     return __builtin_amdgcn_update_dpp(0.0, v, CTRL, 0xf, 0xf, false);
@@ -31,15 +31,30 @@ __device__ __forceinline__ double row_sum16(double v) {
     v += dpp64<0x140>(v);  // row_mirror
     return v;
 }
-// lane l's value of v (readlane on the two 32-bit halves; the builtin's
-// return type is int, so a double must not be passed to it directly)
-__device__ __forceinline__ double rl64(double v, int l) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
+// Cross-row step with the gfx950 row swaps, staying in vector registers: with
+// both operands the same value, permlane16_swap gives every lane of rows
+// (0, 1) the pair (r0, r1) and of rows (2, 3) the pair (r2, r3);
+// permlane32_swap then pairs the two halves.  Every lane ends with
+// (r0 + r1) + (r2 + r3) (op = max: the same association with fmax).
+__device__ __forceinline__ void swap16(double v, double& a, double& b) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    a = __hiloint2double((int)h[0], (int)l[0]);
+    b = __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ void swap32(double v, double& a, double& b) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a = __hiloint2double((int)h[0], (int)l[0]);
+    b = __hiloint2double((int)h[1], (int)l[1]);
 }
 __device__ __forceinline__ double rows_total(double v) {
-    return (rl64(v, 0) + rl64(v, 16)) + (rl64(v, 32) + rl64(v, 48));
+    double a, b;
+    swap16(v, a, b);
+    swap32(a + b, a, b);
+    return a + b;
 }
 __device__ __forceinline__ double wave_sum(double v) { return rows_total(row_sum16(v)); }
 __device__ __forceinline__ double wave_max(double v) {
@@ -47,7 +62,10 @@ __device__ __forceinline__ double wave_max(double v) {
     v = fmax(v, dpp64<0x4E>(v));
     v = fmax(v, dpp64<0x141>(v));
     v = fmax(v, dpp64<0x140>(v));
-    return fmax(fmax(rl64(v, 0), rl64(v, 16)), fmax(rl64(v, 32), rl64(v, 48)));
+    double a, b;
+    swap16(v, a, b);
+    swap32(fmax(a, b), a, b);
+    return fmax(a, b);
 }
 // 1/q for the Sturm recurrence: hardware reciprocal and one Newton step
 // (the step squares the hardware estimate's relative error; the count only
