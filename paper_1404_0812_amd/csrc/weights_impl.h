@@ -67,9 +67,11 @@ __device__ __forceinline__ double wave_max(double v) {
     swap32(fmax(a, b), a, b);
     return fmax(a, b);
 }
-// 1/q for the Sturm recurrence: hardware reciprocal and one Newton step
-// (the step squares the hardware estimate's relative error; the count only
-// needs the sign of each pivot, which the recurrence gets backward-stably)
+// 1/q: hardware reciprocal and one Newton step (the step squares the hardware
+// estimate's relative error).  Used by the Sturm recurrence, whose count only
+// needs the sign of each pivot (which the recurrence gets backward-stably),
+// and by the tridiagonal factorisation, where an error of an ulp or two in a
+// multiplier is a backward perturbation of T of the size GEPP itself leaves.
 __device__ __forceinline__ double recip(double q) {
     const double r = __builtin_amdgcn_rcp(q);
     return fma(r, fma(-q, r, 1.0), r);
@@ -469,10 +471,13 @@ __device__ __forceinline__ bool tri_factor(Shared<NB>& S) {
         const double sub = S.e[i];             // sub-diagonal entry below the pivot
         const double dnext = S.d[i + 1];
         const double unext = i < m - 2 ? S.e[i + 1] : 0.0;
+        // The pivot's reciprocal (hardware reciprocal + one Newton step) gives
+        // the multiplier too, which keeps a full division off the serial chain.
         if (fabs(dcur) >= fabs(sub)) {
             if (dcur == 0.0) return false;
-            const double f = sub / dcur;
-            S.fd[i] = 1.0 / dcur;              // reciprocal of the pivot
+            const double rp = recip(dcur);
+            const double f = sub * rp;
+            S.fd[i] = rp;                      // reciprocal of the pivot
             S.fdu[i] = ucur;
             S.fdl[i] = 0.0;
             S.ffact[i] = f;
@@ -480,8 +485,9 @@ __device__ __forceinline__ bool tri_factor(Shared<NB>& S) {
             dcur = dnext - f * ucur;
             ucur = unext;
         } else {                               // swap rows i and i + 1
-            const double f = dcur / sub;
-            S.fd[i] = 1.0 / sub;
+            const double rp = recip(sub);
+            const double f = dcur * rp;
+            S.fd[i] = rp;
             S.fdu[i] = dnext;
             S.fdl[i] = i < m - 2 ? unext : 0.0;  // second super-diagonal
             S.ffact[i] = f;
@@ -491,7 +497,7 @@ __device__ __forceinline__ bool tri_factor(Shared<NB>& S) {
         }
     }
     if (dcur == 0.0) return false;
-    S.fd[m - 1] = 1.0 / dcur;
+    S.fd[m - 1] = recip(dcur);
     S.fdu[m - 1] = 0.0;
     S.fdl[m - 1] = 0.0;
     return true;
