@@ -34,6 +34,7 @@ def test_learned_mode_band_check_and_fallback(lib, torus):
                             eps_mode="learned", kappa_target=1e12, band=(1e11, 1e13))
     torch.cuda.synchronize()
     st, eg, ne = res.status.cpu().numpy(), res.eps.cpu().numpy(), res.nevals.cpu().numpy()
+    kg = res.kappa.cpu().numpy()
     assert set(np.unique(st)) <= {0, 1}
     assert 0 < np.mean(st == 1) < 1
     for i in rng.choice(len(X), 80, replace=False):
@@ -44,10 +45,31 @@ def test_learned_mode_band_check_and_fallback(lib, torus):
             continue
         if inside:
             assert st[i] == 0 and eg[i] == prop[i] and ne[i] == 1
+            # the kept proposal's kappa_2, searched inside the band's bracket
+            assert abs(kg[i] / k - 1.0) <= 20 * k * 2.0 ** -53
         else:
             assert st[i] == 1
             eo, _, _, _ = bisect_eps(X[idx[i]], 1e12)
             assert abs(eg[i] - eo) <= 2e-4
+
+
+def test_kept_proposals_report_kappa_low_band(lib, torus):
+    """Well-conditioned band [1e5, 1e7]: proposals at the bisected eps for
+    kappa_T = 1e6 are all kept, and their kappa_2 (eigenvalue search stopped at
+    0.05 band_lo u) matches the oracle's to 20 kappa u."""
+    X, nrm, idx = torus
+    Xd, Nd, I = dev(X), dev(nrm), dev(idx, torch.int32)
+    b = lib.build_weights(Xd, Nd, 50, idx=I, eps_mode="bisect", kappa_target=1e6)
+    res = lib.build_weights(Xd, Nd, 50, idx=I, eps_in=b.eps, eps_mode="learned", kappa_target=1e6,
+                            band=(1e5, 1e7))
+    torch.cuda.synchronize()
+    st, kg, eps = res.status.cpu().numpy(), res.kappa.cpu().numpy(), res.eps.cpu().numpy()
+    ok = b.status.cpu().numpy() == 0
+    assert ok.mean() > 0.99 and np.all(st[ok] == 0)
+    assert torch.equal(res.w[torch.as_tensor(ok).cuda()], b.w[torch.as_tensor(ok).cuda()])  # same eps, same weights
+    for i in np.random.default_rng(6).choice(np.flatnonzero(ok), 40, replace=False):
+        k = stencil_kappa(X[idx[i]], eps[i])
+        assert abs(kg[i] / k - 1.0) <= 20 * k * 2.0 ** -53
 
 
 def test_unusable_predictions_reproduce_bisection_bitwise(lib, torus):
