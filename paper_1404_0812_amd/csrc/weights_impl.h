@@ -70,8 +70,9 @@ __device__ __forceinline__ double wave_max(double v) {
 // 1/q: hardware reciprocal and one Newton step (the step squares the hardware
 // estimate's relative error).  Used by the Sturm recurrence, whose count only
 // needs the sign of each pivot (which the recurrence gets backward-stably),
-// and by the tridiagonal factorisation, where an error of an ulp or two in a
-// multiplier is a backward perturbation of T of the size GEPP itself leaves.
+// by the tridiagonal factorisation, where an error of an ulp or two in a
+// multiplier is a backward perturbation of T of the size GEPP itself leaves,
+// and by the Householder reduction (tau and the scale of v).
 __device__ __forceinline__ double recip(double q) {
     const double r = __builtin_amdgcn_rcp(q);
     return fma(r, fma(-q, r, 1.0), r);
@@ -244,8 +245,11 @@ __device__ __forceinline__ void tridiagonalise(double (&a)[64], Shared<NB>& S, c
         double tau = 0.0, beta = alpha, scal = 0.0;
         if (xnorm2 > 0.0) {
             beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
+            // reciprocals instead of divisions: an ulp or so in tau and in the
+            // scale of v, a perturbation of each reflector's orthogonality of
+            // the size its own rounding already leaves
+            tau = (beta - alpha) * recip(beta);
+            scal = recip(alpha - beta);
         }
         const double vi = (c == k + 1) ? 1.0 : (tail ? xi * scal : 0.0);
         if (t.tid == 0) {
