@@ -346,15 +346,21 @@ template <int NB>
 __device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, int rounds, double rel = 0.0) {
     const int m = S.m;
     Spectrum sp;
-    double gl = INFINITY, gu = -INFINITY, emax2 = 0.0;
+    // Gershgorin interval of T: each lane takes rows lane, lane + 64, then
+    // wavefront min/max (exact, so the same bits as a serial scan)
+    double ngl = -INFINITY, gu = -INFINITY, emax2 = 0.0;
     bool fin = true;
-    for (int i = 0; i < m; ++i) {
+    for (int i = lane; i < m; i += 64) {
         const double off = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i < m - 1 ? fabs(S.e[i]) : 0.0);
-        gl = fmin(gl, S.d[i] - off);
+        ngl = fmax(ngl, off - S.d[i]);
         gu = fmax(gu, S.d[i] + off);
         if (i < m - 1) emax2 = fmax(emax2, S.e2[i]);
         fin = fin && isfinite(S.d[i]) && (i == m - 1 || isfinite(S.e[i]));
     }
+    double gl = -wave_max(ngl);
+    gu = wave_max(gu);
+    emax2 = wave_max(emax2);
+    fin = __ballot(!fin) == 0;
     sp.finite = fin;
     sp.pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
     const double w = gu - gl;
