@@ -12,7 +12,7 @@ import pytest
 
 from oracle.knn import knn, knn_bruteforce
 from oracle.shape import bisect_eps, kappa2, stencil_kappa
-from oracle.stepper import assemble, reaction, rk4
+from oracle.stepper import assemble, laplacian_apply, reaction, rk4
 from oracle.truth import stencil_weights_mp
 from oracle.weights import (build_weights, phi, poly_border, psi, stencil_weights,
                             stencil_weights_row1)
@@ -325,6 +325,90 @@ def test_turing_model_equilibrium_from_table1():
     Ru2, Rv2 = reaction("turing", [np.zeros(1), np.array([h])], prm)
     J = np.array([[Ru1[0], Ru2[0]], [Rv1[0], Rv2[0]]]) / h
     assert np.allclose(J, [[prm["alpha"], 1.0], [prm["gamma"], prm["beta"]]], atol=1e-6)
+
+
+def _turing_params(row):
+    g = golden()
+    return {"alpha": g["turing_alpha"], "beta": g["turing_beta"], "gamma": g["turing_gamma"],
+            "tau1": g[f"turing_{row}_tau1"], "tau2": g[f"turing_{row}_tau2"]}
+
+
+@pytest.mark.parametrize("row", ["spots", "stripes"])
+def test_turing_nonlinear_terms_cancel_in_the_sum(row):
+    """Eqs. turing1, turing2: the tau1 (cubic) and tau2 (quadratic) terms enter
+    the two equations with opposite signs, so R_u + R_v is the linear part
+    (alpha + gamma) u + (1 + beta) v for every state.  A wrong sign, power or
+    coefficient in any one nonlinear term breaks this identity."""
+    prm = _turing_params(row)
+    rng = np.random.default_rng(11)
+    u = rng.uniform(-3, 3, 2000)
+    v = rng.uniform(-3, 3, 2000)
+    Ru, Rv = reaction("turing", [u, v], prm)
+    lin = (prm["alpha"] + prm["gamma"]) * u + (1.0 + prm["beta"]) * v
+    scale = np.abs(Ru) + np.abs(Rv) + np.abs(lin)
+    assert np.max(np.abs((Ru + Rv) - lin) / scale) < 1e-14
+
+
+def test_turing_stripes_row_is_odd():
+    """With tau2 = 0 (Table 1, stripes rows) only linear and cubic terms
+    remain, so R(-u, -v) = -R(u, v) exactly."""
+    prm = _turing_params("stripes")
+    assert prm["tau2"] == 0.0
+    rng = np.random.default_rng(12)
+    u = rng.uniform(-3, 3, 500)
+    v = rng.uniform(-3, 3, 500)
+    Ru, Rv = reaction("turing", [u, v], prm)
+    Nu, Nv = reaction("turing", [-u, -v], prm)
+    assert np.array_equal(Nu, -Ru) and np.array_equal(Nv, -Rv)
+
+
+@pytest.mark.parametrize("which,degree", [("tau1", 3), ("tau2", 2)])
+def test_turing_nonlinear_terms_have_their_degree(which, degree):
+    """Eqs. turing1, turing2: the tau1 terms are cubic and the tau2 terms
+    quadratic in (u, v), and both are present in both equations.  Switching one
+    parameter on changes R by a homogeneous polynomial of that degree: scaling
+    the state by s scales the change by s^degree.  (Together with the sum
+    identity this catches a pair of terms dropped or mis-powered together.)"""
+    base = _turing_params("spots")
+    on = dict(base)
+    off = dict(base)
+    off[which] = 0.0
+    other = "tau2" if which == "tau1" else "tau1"
+    on[other] = off[other] = 0.0
+    rng = np.random.default_rng(13)
+    u = rng.uniform(0.2, 1.0, 100)
+    v = rng.uniform(0.2, 1.0, 100)
+    for s in (0.5, 2.0, 3.0):
+        d1 = [a - b for a, b in zip(reaction("turing", [u, v], on), reaction("turing", [u, v], off))]
+        ds = [a - b for a, b in zip(reaction("turing", [s * u, s * v], on), reaction("turing", [s * u, s * v], off))]
+        for a, b in zip(d1, ds):
+            assert np.min(np.abs(a)) > 0.0  # the term is present in this equation
+            assert np.allclose(b, s ** degree * a, rtol=1e-12, atol=0.0)
+
+
+def test_laplacian_apply_equals_sparse_matvec():
+    """(L_X u)_i = sum_k w_ik u_(idx_ik) (Sec. 4: row i of L_X holds stencil i's
+    weights at its node indices) against a dense matrix filled entry by entry
+    and against SciPy's CSR product, on ragged random data: N not a multiple
+    of any tile, odd n, repeated indices inside a row (which add)."""
+    rng = np.random.default_rng(14)
+    for N, n in ((1, 1), (7, 3), (203, 31), (1000, 50)):
+        idx = rng.integers(0, N, size=(N, n))
+        idx[:, 0] = np.arange(N)
+        if n > 2:
+            idx[::3, 2] = idx[::3, 1]  # duplicate column in some rows
+        W = rng.standard_normal((N, n))
+        u = rng.standard_normal(N)
+        got = laplacian_apply(idx, W, u)
+        dense = np.zeros((N, N))
+        for i in range(N):
+            for k in range(n):
+                dense[i, idx[i, k]] += W[i, k]
+        ref = dense @ u
+        csr = assemble(idx, W) @ u
+        tol = 1e-15 * (np.abs(W) @ np.ones(n)) * np.max(np.abs(u)) * n
+        assert np.all(np.abs(got - ref) <= tol)
+        assert np.all(np.abs(got - csr) <= tol)
 
 
 def test_ic_generators_are_seeded():
