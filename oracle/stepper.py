@@ -54,20 +54,29 @@ def reaction(kind: str, Y, params):
     raise ValueError(kind)
 
 
-def rhs(L, Y, D, kind, params):
+def rhs(L, Y, D, kind, params, t=0.0, forcing=None):
+    """du_s/dt = D_s L u_s + R_s(u) + f_s(t) (eq. diffusion_scalar with the
+    forcing of Sec. 6).  forcing = (lam, F): f_s(t, x_i) = exp(lam t) F[s][i],
+    the form of the manufactured solutions (eqs. sph_forced, torus_forced)."""
     R = reaction(kind, Y, params)
-    return [D[s] * (L @ Y[s]) + R[s] for s in range(len(Y))]
+    out = [D[s] * (L @ Y[s]) + R[s] for s in range(len(Y))]
+    if forcing is not None:
+        lam, F = forcing
+        out = [out[s] + np.exp(lam * t) * F[s] for s in range(len(Y))]
+    return out
 
 
-def rk4(L, Y0, D, kind="none", params=None, dt=1e-4, nsteps=1):
-    """Classical RK4: k1 = f(y), k2 = f(y + dt/2 k1), k3 = f(y + dt/2 k2),
-    k4 = f(y + dt k3), y+ = y + dt/6 (k1 + 2 k2 + 2 k3 + k4)."""
+def rk4(L, Y0, D, kind="none", params=None, dt=1e-4, nsteps=1, t0=0.0, forcing=None):
+    """Classical RK4 from time t0: k1 = f(t, y), k2 = f(t + dt/2, y + dt/2 k1),
+    k3 = f(t + dt/2, y + dt/2 k2), k4 = f(t + dt, y + dt k3),
+    y+ = y + dt/6 (k1 + 2 k2 + 2 k3 + k4)."""
     Y = [np.array(y, dtype=np.float64) for y in Y0]
     S = len(Y)
-    for _ in range(nsteps):
-        k1 = rhs(L, Y, D, kind, params)
-        k2 = rhs(L, [Y[s] + 0.5 * dt * k1[s] for s in range(S)], D, kind, params)
-        k3 = rhs(L, [Y[s] + 0.5 * dt * k2[s] for s in range(S)], D, kind, params)
-        k4 = rhs(L, [Y[s] + dt * k3[s] for s in range(S)], D, kind, params)
+    for i in range(nsteps):
+        t = t0 + i * dt
+        k1 = rhs(L, Y, D, kind, params, t, forcing)
+        k2 = rhs(L, [Y[s] + 0.5 * dt * k1[s] for s in range(S)], D, kind, params, t + 0.5 * dt, forcing)
+        k3 = rhs(L, [Y[s] + 0.5 * dt * k2[s] for s in range(S)], D, kind, params, t + 0.5 * dt, forcing)
+        k4 = rhs(L, [Y[s] + dt * k3[s] for s in range(S)], D, kind, params, t + dt, forcing)
         Y = [Y[s] + (dt / 6.0) * (k1[s] + 2.0 * k2[s] + 2.0 * k3[s] + k4[s]) for s in range(S)]
     return Y

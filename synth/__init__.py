@@ -12,10 +12,17 @@ from .nodes import (  # noqa: F401
     blob,
     planar_patch,
     surface_batch,
+    icosahedral_sphere,
+    staggered_torus,
+    torus_angles,
     cached,
 )
 from .fields import (  # noqa: F401
     real_sph_harm,
     random_sph_harm_ic,
     schnakenberg_ic,
+    sphere_heat_series,
+    bump_centres,
+    sphere_forced,
+    torus_forced,
 )

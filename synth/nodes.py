@@ -26,6 +26,9 @@ __all__ = [
     "blob",
     "planar_patch",
     "surface_batch",
+    "icosahedral_sphere",
+    "staggered_torus",
+    "torus_angles",
     "cached",
 ]
 
@@ -247,6 +250,70 @@ def surface_batch(count: int = 64, seed: int = 5, n_min: int = 2000, n_max: int 
             params = {"axes": ax.tolist()}
         out.append({"kind": kind, "X": X, "nrm": nrm, "n": n, "params": params})
     return out
+
+
+def icosahedral_sphere(level: int):
+    """Icosahedral nodes on the unit sphere (the node sets of Sec. 6.1).
+
+    The 12 vertices of an icosahedron; every triangle is split into four by
+    its edge midpoints, pushed out to the sphere, `level` times.  N = 10 4^level
+    + 2 (642, 2562, 10242, 40962 for levels 3..6).  Normals are the exact unit
+    normals (the node directions).
+    """
+    g = (1.0 + math.sqrt(5.0)) / 2.0
+    V = [(-1, g, 0), (1, g, 0), (-1, -g, 0), (1, -g, 0), (0, -1, g), (0, 1, g), (0, -1, -g), (0, 1, -g),
+         (g, 0, -1), (g, 0, 1), (-g, 0, -1), (-g, 0, 1)]
+    V = [np.array(v, dtype=np.float64) / math.sqrt(1.0 + g * g) for v in V]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5), (2, 4, 11),
+         (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in mid:
+                v = V[a] + V[b]
+                V.append(v / np.linalg.norm(v))
+                mid[key] = len(V) - 1
+            return mid[key]
+
+        F2 = []
+        for a, b, c in F:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            F2 += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = F2
+    X = np.array(V)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    return X, X.copy()
+
+
+def staggered_torus(m: int, R: float = 1.0, r: float = 1.0 / 3.0):
+    """The staggered grid on the torus of Sec. 6.1 (eq. torus): m angles in
+    phi and 3m in lam, equally spaced on [-pi, pi) (the endpoint pi dropped),
+    their direct product, and the same grid shifted by half a cell in both
+    angles (pi/m in phi, pi/(3m) in lam).  N = 6 m^2 (600, 2400, 5400,
+    21600, 38400 for m = 10, 20, 30, 60, 80).  Normals are analytic."""
+    phi0 = -math.pi + 2.0 * math.pi * np.arange(m) / m
+    lam0 = -math.pi + 2.0 * math.pi * np.arange(3 * m) / (3 * m)
+    out_p, out_l = [], []
+    for dp, dl in ((0.0, 0.0), (math.pi / m, math.pi / (3 * m))):
+        P, L = np.meshgrid(phi0 + dp, lam0 + dl, indexing="ij")
+        out_p.append(P.ravel())
+        out_l.append(L.ravel())
+    phi = np.concatenate(out_p)
+    lam = np.concatenate(out_l)
+    c = R + r * np.cos(phi)
+    X = np.stack([c * np.cos(lam), c * np.sin(lam), r * np.sin(phi)], axis=1)
+    nrm = np.stack([np.cos(phi) * np.cos(lam), np.cos(phi) * np.sin(lam), np.sin(phi)], axis=1)
+    return X, nrm
+
+
+def torus_angles(X: np.ndarray, R: float = 1.0):
+    """Intrinsic angles (phi, lam) of points on the torus of eq. torus."""
+    lam = np.arctan2(X[:, 1], X[:, 0])
+    phi = np.arctan2(X[:, 2], np.hypot(X[:, 0], X[:, 1]) - R)
+    return phi, lam
 
 
 def cached(fn, *args, **kw):
