@@ -43,6 +43,7 @@ typedef struct rbffd_op_s* rbffd_op;
 #define RBFFD_E_HIP (-2)      /* a HIP runtime call failed */
 #define RBFFD_E_NOMEM (-3)    /* device allocation of library scratch failed */
 #define RBFFD_E_UNSUPPORTED (-4) /* valid request outside what this library implements */
+#define RBFFD_E_NONFINITE (-5) /* rbffd_step: the state became non-finite (NaN or Inf) */
 
 /* radial kernels (Sec. 2) */
 #define RBFFD_KERNEL_MQ 0  /* sqrt(1 + (eps r)^2) */
@@ -64,6 +65,9 @@ typedef struct rbffd_op_s* rbffd_op;
 #define RBFFD_ST_SINGULAR 4   /* zero pivot in the tridiagonal solve */
 #define RBFFD_ST_DUPLICATE 5  /* two stencil nodes coincide */
 #define RBFFD_ST_BAD_INDEX 6  /* a stencil index outside [0, N): weights NaN, stencil skipped */
+#define RBFFD_ST_BAD_NORMAL 7 /* a stencil node's normal is zero or not finite (the projection
+                                 Pi = I - nu nu^T of Sec. 3 is undefined): eps, kappa and
+                                 weights NaN, stencil skipped */
 
 /* reaction terms for rbffd_step */
 #define RBFFD_REACT_NONE 0
@@ -211,9 +215,15 @@ int rbffd_autotune_batched(rbffd_ctx ctx, int32_t nsurf, const rbffd_surface* su
  * identity), in FP64 and, for FP32 stepping, as FP32 off-diagonal weights
  * for the difference form sum_{j != i} w_ij (u_j - u_i).  *out is a HOST
  * pointer.  The operator owns device memory freed by rbffd_op_destroy.
+ * Requirements on the rows: slot 0 of row i is node i itself (idx[i*n] ==
+ * i, the layout rbffd_knn and rbffd_build_weights produce), and for FP32
+ * stepping each row's weights sum to zero (L_X reproduces constants, as the
+ * RBF-FD weights of Sec. 4 do): the FP32 form drops slot 0 and uses the
+ * differences u_j - u_i, which equals L u only under that condition.
  * Errors: N < 1, n < 2, n > 128, n > N, null idx or w; an idx entry outside
- * [0, N) or a perm that is not a permutation of 0..N-1 (checked on the
- * device; the call then synchronises and returns RBFFD_E_ARG).
+ * [0, N), a row whose slot 0 is not the row itself, or a perm that is not a
+ * permutation of 0..N-1 (checked on the device; the call then synchronises
+ * and returns RBFFD_E_ARG).
  */
 int rbffd_op_create(rbffd_ctx ctx, int64_t N, int32_t n, const int32_t* idx, const double* w,
                     const int32_t* perm, rbffd_op* out);
@@ -259,12 +269,32 @@ int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const double* u, doubl
  * diffusivities (HOST).  params: reaction parameters (HOST, see
  * RBFFD_REACT_*).  prec selects FP64 or FP32 state arithmetic (FP32 uses the
  * difference form).  Steps run as a captured HIP graph of `graph_steps`
- * steps (0 = library default), replayed as needed.
+ * steps (0 = library default), replayed as needed.  The last stage of every
+ * step raises a device flag when a state value is not finite; the flag is
+ * copied to the host after each graph replay, further replays are skipped
+ * once a copied flag shows it, and the call ends by synchronising the
+ * context's stream (unlike the other calls, it returns after the work is
+ * done) and returns RBFFD_E_NONFINITE if the flag was raised (state then
+ * holds the last, non-finite values).
  * Errors: nspecies not 1 or 2, a reaction needing 2 species given 1, dt <= 0.
  */
 int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec,
                const double* D, int32_t reaction, const double* params, double dt, int64_t nsteps,
                int32_t graph_steps);
+
+/*
+ * rbffd_step with a forcing term f (eq. diffusion_scalar of Sec. 4.2:
+ * du/dt = delta L_X u + f) of the separable form of the manufactured
+ * solutions of Sec. 6 (eqs. sph_forced, torus_forced):
+ *   f_s(t, x_i) = exp(lambda t) forcing[s * N + i],
+ * forcing: nspecies x N FP64, caller order (read once per call).  The state
+ * is at time t0 on entry; RK4 evaluates f at the stage times t_n, t_n + dt/2,
+ * t_n + dt/2, t_n + dt.  Otherwise as rbffd_step.
+ * Errors: as rbffd_step; null forcing; t0 or lambda not finite.
+ */
+int rbffd_step_forced(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec,
+                      const double* D, int32_t reaction, const double* params, double dt, int64_t nsteps,
+                      int32_t graph_steps, double t0, const double* forcing, double lambda);
 
 /* ------------------------------------------------------------------------
  * Learned shape parameter.  A 128 -> 128 -> 128 -> 1 ReLU network maps a

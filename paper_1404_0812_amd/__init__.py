@@ -22,7 +22,7 @@ EPS_MODES = {"fixed": 0, "given": 1, "bisect": 2, "learned": 3}
 REACTIONS = {"none": 0, "schnakenberg": 1, "turing": 2}
 PRECS = {"f64": 0, "f32": 1}
 
-ST_OK, ST_FALLBACK, ST_NO_BRACKET, ST_NONFINITE, ST_SINGULAR, ST_DUPLICATE, ST_BAD_INDEX = range(7)
+ST_OK, ST_FALLBACK, ST_NO_BRACKET, ST_NONFINITE, ST_SINGULAR, ST_DUPLICATE, ST_BAD_INDEX, ST_BAD_NORMAL = range(8)
 
 
 class RbffdError(RuntimeError):
@@ -343,18 +343,31 @@ class Operator:
         self.ctx.leave()
         return out
 
-    def step(self, state, dt, nsteps, prec="f64", D=(1.0,), reaction="none", params=(), graph_steps=0):
-        """Advance state (S x N float64, S = 1 or 2) by nsteps RK4 steps; returns the new state."""
+    def step(self, state, dt, nsteps, prec="f64", D=(1.0,), reaction="none", params=(), graph_steps=0,
+             forcing=None, t0=0.0, lam=0.0):
+        """Advance state (S x N float64, S = 1 or 2) by nsteps RK4 steps; returns the new state.
+
+        forcing (S x N float64, optional): f_s(t, x_i) = exp(lam t) forcing[s, i],
+        the state being at time t0 on entry.  Raises RbffdError if the state
+        becomes non-finite."""
         st = _dev(state, torch.float64, "state").clone()
         if st.dim() == 1:
             st = st.unsqueeze(0)
         S = st.shape[0]
         Darr = (ctypes.c_double * max(2, len(D)))(*[float(x) for x in D])
         prm = (ctypes.c_double * 5)(*([float(x) for x in params] + [0.0] * (5 - len(params))))
-        self.ctx.enter(st)
-        self.ctx.check(self.ctx.lib.rbffd_step(self.ctx.h, self.h, S, _ptr(st), PRECS[prec], Darr,
-                                               REACTIONS[reaction], prm, float(dt), int(nsteps), int(graph_steps)))
+        if forcing is None:
+            self.ctx.enter(st)
+            rc = self.ctx.lib.rbffd_step(self.ctx.h, self.h, S, _ptr(st), PRECS[prec], Darr,
+                                         REACTIONS[reaction], prm, float(dt), int(nsteps), int(graph_steps))
+        else:
+            F = _dev(forcing, torch.float64, "forcing").reshape(st.shape)
+            self.ctx.enter(st, F)
+            rc = self.ctx.lib.rbffd_step_forced(self.ctx.h, self.h, S, _ptr(st), PRECS[prec], Darr,
+                                                REACTIONS[reaction], prm, float(dt), int(nsteps), int(graph_steps),
+                                                float(t0), _ptr(F), float(lam))
         self.ctx.leave()
+        self.ctx.check(rc)
         return st
 
 

@@ -112,6 +112,9 @@ SIGNATURES = {
     "rbffd_apply": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rbffd_step": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double), c_int32,
                              ctypes.POINTER(c_double), c_double, c_int64, c_int32]),
+    "rbffd_step_forced": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double),
+                                    c_int32, ctypes.POINTER(c_double), c_double, c_int64, c_int32, c_double,
+                                    c_void_p, c_double]),
     "rbffd_mlp_features": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_void_p,
                                      c_void_p]),
     "rbffd_mlp_forward": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p, c_void_p]),

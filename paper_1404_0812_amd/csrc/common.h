@@ -59,6 +59,11 @@ struct rbffd_op_s {
     double graph_key_dt = 0.0;
     double graph_key_D[2] = {0, 0};
     double graph_key_params[5] = {0, 0, 0, 0, 0};
+    int graph_key_forced = 0;
+    double graph_key_t0 = 0.0, graph_key_lam = 0.0;
+    // device: int64 steps done by the forced stages, then int non-finite flag
+    void* counters = nullptr;
+    int* nonfinite_host = nullptr;  // pinned host copy of the flag
 };
 
 int set_error(rbffd_ctx ctx, int code, const char* fmt, ...);

@@ -21,6 +21,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -69,6 +70,8 @@ __global__ void k_build_sell(int64_t N, int n, int64_t row0, int64_t col0, const
     const int64_t q = row0 + p;
     const OpSlice sl = slices[q >> 6];
     const int r = (int)(q & 63);
+    // slot 0 must be the row's own node: the FP32 difference form drops it
+    if (idx[i * n] != i) *bad = 1;
     for (int k = 0; k < n; ++k) {
         const int32_t c = idx[i * n + k];
         const int32_t ip = (c >= 0 && c < N) ? iperm[c] : -1;
@@ -221,6 +224,13 @@ struct StageArgs {
     double D[2];
     double dt;
     ReactParams rp;
+    int* nonfinite;         // set to 1 by the last stage when a state value is not finite
+    // forcing f_s(t, x_p) = exp(lam t) F[p S + s] (FORCED kernels only): the
+    // stage time is t0 + (*steps_done + step_in_launch + c_stage) dt, with
+    // *steps_done advanced on the device after each launch sequence
+    const void* F;
+    double lam, t0, toff;   // toff = (step_in_launch + c_stage), set per launch
+    const int64_t* steps_done;
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs; remap them so that each
@@ -465,7 +475,7 @@ __device__ __forceinline__ void laplacian_row(const StageArgs& a, const RowPos& 
 // RK4 stage `ST` (0..3).  Y: stage input; U: state at the start of the step;
 // ACC: accumulator; YN: next stage input (stages 0-2) -- stage 3 updates U
 // (FP32: YN is then the compensation term of the update).
-template <typename T, int S, int R, int ST>
+template <typename T, int S, int R, int ST, bool FORCED>
 __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* __restrict__ idx,
                                                    const T* __restrict__ w, const T* __restrict__ Y,
                                                    T* __restrict__ U, T* __restrict__ ACC, T* __restrict__ YN) {
@@ -482,6 +492,14 @@ __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* _
     T k[2];
     k[0] = (T)a.D[0] * lap[0] + r[0];
     k[1] = (T)a.D[1] * lap[1] + r[1];
+    if constexpr (FORCED) {
+        const double t = a.t0 + ((double)*a.steps_done + a.toff) * a.dt;  // uniform
+        const T ef = (T)exp(a.lam * t);
+        T f[2];
+        vload<T, S>(reinterpret_cast<const T*>(a.F), p, f);
+        k[0] = fma(ef, f[0], k[0]);
+        k[1] = fma(ef, f[1], k[1]);
+    }
     const T dt = (T)a.dt;
     T u[2], c[2], o[2];
     if (ST == 0) {
@@ -523,7 +541,15 @@ __global__ __launch_bounds__(BLK) void k_rk4_stage(StageArgs a, const int32_t* _
             o[1] = u[1] + dt / (T)6 * (c[1] + k[1]);
             vstore<T, S>(U, p, o);
         }
+        if (!(isfinite(o[0]) && isfinite(o[1]))) *a.nonfinite = 1;  // every writer stores 1
     }
+}
+
+// Device-side step counter of the forced stages, advanced after each launch sequence.
+__global__ void k_advance_steps(int64_t* steps_done, int64_t by) { *steps_done += by; }
+__global__ void k_set_steps(int64_t* steps_done, int* nonfinite) {
+    *steps_done = 0;
+    *nonfinite = 0;
 }
 
 // one operator application (stage-free): out = L y (reaction-free, D = 1)
@@ -542,36 +568,49 @@ __global__ __launch_bounds__(BLK) void k_apply(StageArgs a, const int32_t* __res
 // blocks of one stage launch: four slices each
 inline dim3 stage_grid(int64_t nslices) { return dim3((unsigned)((nslices + BLK / 64 - 1) / (BLK / 64))); }
 
-template <typename T, int S, int R>
-void enqueue_step(hipStream_t st, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC, T* Y1, T* Y2,
-                  T* COMP) {
+// One RK4 step, the i-th of its launch sequence; stage times t_n + c dt with
+// c = 0, 1/2, 1/2, 1.
+template <typename T, int S, int R, bool FORCED>
+void enqueue_step(hipStream_t st, StageArgs a, int64_t i, const int32_t* idx, const T* w, T* U, T* ACC, T* Y1,
+                  T* Y2, T* COMP) {
     const dim3 g = stage_grid(a.nslices), b(BLK);
-    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 0>), g, b, 0, st, a, idx, w, U, U, ACC, Y1);
-    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 1>), g, b, 0, st, a, idx, w, Y1, U, ACC, Y2);
-    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 2>), g, b, 0, st, a, idx, w, Y2, U, ACC, Y1);
-    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 3>), g, b, 0, st, a, idx, w, Y1, U, ACC, COMP);
+    a.toff = (double)i;
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 0, FORCED>), g, b, 0, st, a, idx, w, U, U, ACC, Y1);
+    a.toff = (double)i + 0.5;
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 1, FORCED>), g, b, 0, st, a, idx, w, Y1, U, ACC, Y2);
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 2, FORCED>), g, b, 0, st, a, idx, w, Y2, U, ACC, Y1);
+    a.toff = (double)i + 1.0;
+    hipLaunchKernelGGL((k_rk4_stage<T, S, R, 3, FORCED>), g, b, 0, st, a, idx, w, Y1, U, ACC, COMP);
+}
+
+template <typename T, bool FORCED>
+void enqueue_steps_f(hipStream_t st, int S, int R, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC,
+                     T* COMP, T* Y1, T* Y2, int64_t steps) {
+    for (int64_t i = 0; i < steps; ++i) {
+        if (S == 1) {
+            enqueue_step<T, 1, RBFFD_REACT_NONE, FORCED>(st, a, i, idx, w, U, ACC, Y1, Y2, COMP);
+        } else if (R == RBFFD_REACT_SCHNAKENBERG) {
+            enqueue_step<T, 2, RBFFD_REACT_SCHNAKENBERG, FORCED>(st, a, i, idx, w, U, ACC, Y1, Y2, COMP);
+        } else if (R == RBFFD_REACT_TURING) {
+            enqueue_step<T, 2, RBFFD_REACT_TURING, FORCED>(st, a, i, idx, w, U, ACC, Y1, Y2, COMP);
+        } else {
+            enqueue_step<T, 2, RBFFD_REACT_NONE, FORCED>(st, a, i, idx, w, U, ACC, Y1, Y2, COMP);
+        }
+    }
+    // forced stages read the step counter: advance it past this sequence
+    if (FORCED) hipLaunchKernelGGL(k_advance_steps, dim3(1), dim3(1), 0, st, const_cast<int64_t*>(a.steps_done), steps);
 }
 
 template <typename T>
 void enqueue_steps_t(hipStream_t st, int S, int R, const StageArgs& a, const int32_t* idx, const T* w, T* U, T* ACC,
-                     T* COMP,
-                     T* Y1, T* Y2, int64_t steps) {
-    for (int64_t i = 0; i < steps; ++i) {
-        if (S == 1) {
-            enqueue_step<T, 1, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
-        } else if (R == RBFFD_REACT_SCHNAKENBERG) {
-            enqueue_step<T, 2, RBFFD_REACT_SCHNAKENBERG>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
-        } else if (R == RBFFD_REACT_TURING) {
-            enqueue_step<T, 2, RBFFD_REACT_TURING>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
-        } else {
-            enqueue_step<T, 2, RBFFD_REACT_NONE>(st, a, idx, w, U, ACC, Y1, Y2, COMP);
-        }
-    }
+                     T* COMP, T* Y1, T* Y2, int64_t steps) {
+    if (a.F) enqueue_steps_f<T, true>(st, S, R, a, idx, w, U, ACC, COMP, Y1, Y2, steps);
+    else enqueue_steps_f<T, false>(st, S, R, a, idx, w, U, ACC, COMP, Y1, Y2, steps);
 }
 
 int ensure_work(rbffd_op op) {
-    // 4 buffers (U, ACC, Y1, Y2) x 2 species x FP64
-    size_t need = 4 * 2 * (size_t)op->P * sizeof(double);
+    // 4 buffers (U, ACC, Y1, Y2) x 2 species x FP64, and the forcing (2 species)
+    size_t need = 5 * 2 * (size_t)op->P * sizeof(double);
     if (op->work_bytes >= need) return RBFFD_OK;
     if (op->work) {
         (void)hipStreamSynchronize(op->ctx->stream);
@@ -639,6 +678,8 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
               hipMalloc(&op->lidx, std::max<int64_t>(1, off32) * sizeof(uint16_t)) == hipSuccess &&
               hipMalloc(&op->halo, std::max<size_t>(1, sl.size()) * OP_HALO_MAX * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&op->perm, std::max<int64_t>(1, P) * sizeof(int32_t)) == hipSuccess;
+    ok = ok && hipMalloc(&op->counters, sizeof(int64_t) + sizeof(int)) == hipSuccess &&
+         hipHostMalloc(reinterpret_cast<void**>(&op->nonfinite_host), sizeof(int), hipHostMallocDefault) == hipSuccess;
     int32_t* iperm = nullptr;
     int* bad = nullptr;
     ok = ok && hipMalloc(&iperm, std::max<int64_t>(1, maxN) * sizeof(int32_t)) == hipSuccess;
@@ -737,6 +778,8 @@ extern "C" int rbffd_op_destroy(rbffd_op op) {
     if (op->halo) (void)hipFree(op->halo);
     if (op->perm) (void)hipFree(op->perm);
     if (op->work) (void)hipFree(op->work);
+    if (op->counters) (void)hipFree(op->counters);
+    if (op->nonfinite_host) (void)hipHostFree(op->nonfinite_host);
     delete op;
     return RBFFD_OK;
 }
@@ -795,8 +838,11 @@ extern "C" int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const doubl
     return RBFFD_OK;
 }
 
-extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec, const double* D,
-                          int32_t reaction, const double* params, double dt, int64_t nsteps, int32_t graph_steps) {
+namespace {
+
+int step_impl(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec, const double* D,
+              int32_t reaction, const double* params, double dt, int64_t nsteps, int32_t graph_steps, double t0,
+              const double* forcing, double lam) {
     if (!ctx || !op || !state || !D) return set_error(ctx, RBFFD_E_ARG, "null argument");
     if (nspecies != 1 && nspecies != 2) return set_error(ctx, RBFFD_E_ARG, "nspecies must be 1 or 2");
     if (prec != RBFFD_F64 && prec != RBFFD_F32) return set_error(ctx, RBFFD_E_ARG, "prec must be F64 or F32");
@@ -807,6 +853,8 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     if (!(dt > 0.0)) return set_error(ctx, RBFFD_E_ARG, "dt must be > 0");
     if (nsteps < 0) return set_error(ctx, RBFFD_E_ARG, "nsteps must be >= 0");
     if (graph_steps < 0) return set_error(ctx, RBFFD_E_ARG, "graph_steps must be >= 0");
+    if (forcing && !(std::isfinite(t0) && std::isfinite(lam)))
+        return set_error(ctx, RBFFD_E_ARG, "t0 and lambda must be finite");
     op->ctx = ctx;
     int rc = ensure_work(op);
     if (rc) return rc;
@@ -824,6 +872,10 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     a.dt = dt;
     const int np = reaction == RBFFD_REACT_SCHNAKENBERG ? 3 : (reaction == RBFFD_REACT_TURING ? 5 : 0);
     for (int i = 0; i < np; ++i) a.rp.p[i] = params[i];
+    int64_t* steps_done = reinterpret_cast<int64_t*>(op->counters);
+    int* nonfinite = reinterpret_cast<int*>(reinterpret_cast<char*>(op->counters) + sizeof(int64_t));
+    a.nonfinite = nonfinite;
+    a.steps_done = steps_done;
     const int G = graph_steps > 0 ? graph_steps : 50;
     const size_t esz = prec == RBFFD_F64 ? sizeof(double) : sizeof(float);
     char* base = (char*)op->work;
@@ -833,12 +885,22 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     void* Y2 = base + 6 * P * esz;
     // FP32: compensation of the state update (inside the FP64-sized work area)
     void* COMP = prec == RBFFD_F64 ? nullptr : (void*)(base + 8 * P * esz);
+    void* FI = base + 8 * P * sizeof(double);  // forcing in internal order, after the FP64 buffers
+    if (forcing) {
+        a.F = FI;
+        a.lam = lam;
+        a.t0 = t0;
+    }
     const int32_t* idx = prec == RBFFD_F64 ? op->idx64 : op->idx32;
     const void* w = prec == RBFFD_F64 ? (const void*)op->w64 : (const void*)op->w32;
+    // counters are cleared by a kernel (no memset node near the captured graph)
+    hipLaunchKernelGGL(k_set_steps, dim3(1), dim3(1), 0, st, steps_done, nonfinite);
     if (prec == RBFFD_F64) {
         hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, nspecies, state, op->perm, (double*)U);
+        if (forcing) hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, nspecies, forcing, op->perm, (double*)FI);
     } else {
         hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, P, N, nspecies, state, op->perm, (float*)U);
+        if (forcing) hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, P, N, nspecies, forcing, op->perm, (float*)FI);
         HIP_TRY(ctx, hipMemsetAsync(COMP, 0, 2 * (size_t)P * sizeof(float), st));  // outside any captured graph
     }
     HIP_TRY(ctx, hipGetLastError());
@@ -853,11 +915,16 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
     };
     const int64_t reps = nsteps / G;
     const int64_t rest = nsteps % G;
+    volatile int* nf_host = reinterpret_cast<volatile int*>(op->nonfinite_host);
+    *nf_host = 0;
+    bool stopped = false;
     if (reps > 0) {
+        const int forced = forcing ? 1 : 0;
         bool same = op->graph && op->graph_key_species == nspecies && op->graph_key_prec == prec &&
                     op->graph_key_react == reaction && op->graph_key_steps == G && op->graph_key_dt == dt &&
                     op->graph_key_D[0] == a.D[0] && op->graph_key_D[1] == a.D[1] &&
-                    std::memcmp(op->graph_key_params, a.rp.p, sizeof(a.rp.p)) == 0;
+                    std::memcmp(op->graph_key_params, a.rp.p, sizeof(a.rp.p)) == 0 &&
+                    op->graph_key_forced == forced && (!forced || (op->graph_key_t0 == t0 && op->graph_key_lam == lam));
         if (!same) {
             reset_graph(op);
             hipGraph_t graph;
@@ -879,14 +946,46 @@ extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* 
             op->graph_key_D[0] = a.D[0];
             op->graph_key_D[1] = a.D[1];
             std::memcpy(op->graph_key_params, a.rp.p, sizeof(a.rp.p));
+            op->graph_key_forced = forced;
+            op->graph_key_t0 = t0;
+            op->graph_key_lam = lam;
         }
-        for (int64_t r = 0; r < reps; ++r) HIP_TRY(ctx, hipGraphLaunch(op->graph, st));
+        for (int64_t r = 0; r < reps; ++r) {
+            // the flag copied after an earlier replay has already landed: stop on a blow-up
+            if (*nf_host) {
+                stopped = true;
+                break;
+            }
+            HIP_TRY(ctx, hipGraphLaunch(op->graph, st));
+            HIP_TRY(ctx, hipMemcpyAsync(op->nonfinite_host, nonfinite, sizeof(int), hipMemcpyDeviceToHost, st));
+        }
     }
-    if (rest > 0) enqueue(st, rest);
+    if (rest > 0 && !stopped) enqueue(st, rest);
     if (prec == RBFFD_F64)
         hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, P, N, nspecies, (const double*)U, op->perm, state);
     else
         hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, P, N, nspecies, (const float*)U, op->perm, state);
     HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(op->nonfinite_host, nonfinite, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (*nf_host)
+        return set_error(ctx, RBFFD_E_NONFINITE,
+                         "the state became non-finite (steps stopped early; state holds the last values)");
     return RBFFD_OK;
+}
+
+}  // namespace
+
+extern "C" int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec, const double* D,
+                          int32_t reaction, const double* params, double dt, int64_t nsteps, int32_t graph_steps) {
+    return step_impl(ctx, op, nspecies, state, prec, D, reaction, params, dt, nsteps, graph_steps, 0.0, nullptr,
+                     0.0);
+}
+
+extern "C" int rbffd_step_forced(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec,
+                                 const double* D, int32_t reaction, const double* params, double dt, int64_t nsteps,
+                                 int32_t graph_steps, double t0, const double* forcing, double lambda) {
+    if (!forcing) return set_error(ctx, RBFFD_E_ARG, "forcing is required");
+    return step_impl(ctx, op, nspecies, state, prec, D, reaction, params, dt, nsteps, graph_steps, t0, forcing,
+                     lambda);
 }

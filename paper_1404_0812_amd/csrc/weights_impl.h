@@ -334,14 +334,53 @@ __device__ __forceinline__ int sturm(const Shared<NB>& S, int m, double sigma, d
 }
 
 struct Spectrum {
-    double amax;  // max |lambda|
+    double amax;  // max |lambda| (midpoint estimate)
     bool finite;
     double pivmin;
+    // multisection brackets: lambda_1 in [lo1, hi1], lambda_m in [lo2, hi2]
+    double lo1, hi1, lo2, hi2;
 };
 
-// Largest |lambda| of T to ~33^-rounds of the Gershgorin width; with rel > 0
-// the multisection stops as soon as both brackets are within 2 rel of the
-// current estimate of max |lambda| (midpoint error <= rel relative).
+// max |lambda| = max(-lambda_1, lambda_m) lies in [alo, ahi].
+__device__ __forceinline__ void amax_bounds(const Spectrum& sp, double& alo, double& ahi) {
+    alo = fmax(-sp.hi1, sp.lo2);
+    ahi = fmax(-sp.lo1, sp.hi2);
+}
+
+// Up to `rounds` more 33-way multisection rounds on the brackets of lambda_1
+// (lanes 0..31) and lambda_m (lanes 32..63); with rel > 0 the rounds stop as
+// soon as both brackets are within 2 rel of the current estimate of
+// max |lambda| (midpoint error <= rel relative).
+template <int NB>
+__device__ __forceinline__ void spectrum_refine(const Shared<NB>& S, int lane, Spectrum& sp, int rounds,
+                                                double rel = 0.0) {
+    const int m = S.m;
+    double lo1 = sp.lo1, hi1 = sp.hi1, lo2 = sp.lo2, hi2 = sp.hi2;
+    const int g = lane >> 5, tt = lane & 31;
+    for (int rd = 0; rd < rounds; ++rd) {
+        if (rel > 0.0) {  // uniform: the brackets are wave-uniform
+            const double est = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
+            if (fmax(hi1 - lo1, hi2 - lo2) <= 2.0 * rel * est) break;
+        }
+        const double lo = g ? lo2 : lo1, hi = g ? hi2 : hi1;
+        const double sig = lo + (hi - lo) * (double)(tt + 1) / 33.0;
+        const int kidx = g ? m : 1;
+        const bool below = sturm<NB>(S, m, sig, sp.pivmin) < kidx;  // eigenvalue kidx lies above sig
+        const uint64_t bal = __ballot(below);
+        const int nb1 = __popcll(bal & 0xffffffffull);
+        const int nb2 = __popcll(bal >> 32);
+        const double n_lo1 = nb1 > 0 ? lo1 + (hi1 - lo1) * (double)nb1 / 33.0 : lo1;
+        const double n_hi1 = nb1 < 32 ? lo1 + (hi1 - lo1) * (double)(nb1 + 1) / 33.0 : hi1;
+        const double n_lo2 = nb2 > 0 ? lo2 + (hi2 - lo2) * (double)nb2 / 33.0 : lo2;
+        const double n_hi2 = nb2 < 32 ? lo2 + (hi2 - lo2) * (double)(nb2 + 1) / 33.0 : hi2;
+        lo1 = n_lo1; hi1 = n_hi1; lo2 = n_lo2; hi2 = n_hi2;
+    }
+    sp.lo1 = lo1; sp.hi1 = hi1; sp.lo2 = lo2; sp.hi2 = hi2;
+    sp.amax = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
+}
+
+// Largest |lambda| of T to ~33^-rounds of the Gershgorin width (see
+// spectrum_refine for rel).
 template <int NB>
 __device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, int rounds, double rel = 0.0) {
     const int m = S.m;
@@ -366,32 +405,13 @@ __device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, 
     const double w = gu - gl;
     gl -= 2.0 * w * 2.2e-16 + 2.0 * sp.pivmin;
     gu += 2.0 * w * 2.2e-16 + 2.0 * sp.pivmin;
+    sp.lo1 = sp.lo2 = gl;
+    sp.hi1 = sp.hi2 = gu;
     if (!fin) {
         sp.amax = NAN;
         return sp;
     }
-    // lanes 0..31: smallest eigenvalue (index 1); lanes 32..63: largest (index m)
-    double lo1 = gl, hi1 = gu, lo2 = gl, hi2 = gu;
-    const int g = lane >> 5, tt = lane & 31;
-    for (int rd = 0; rd < rounds; ++rd) {
-        if (rel > 0.0) {  // uniform: the brackets are wave-uniform
-            const double est = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
-            if (fmax(hi1 - lo1, hi2 - lo2) <= 2.0 * rel * est) break;
-        }
-        const double lo = g ? lo2 : lo1, hi = g ? hi2 : hi1;
-        const double sig = lo + (hi - lo) * (double)(tt + 1) / 33.0;
-        const int kidx = g ? m : 1;
-        const bool below = sturm<NB>(S, m, sig, sp.pivmin) < kidx;  // eigenvalue kidx lies above sig
-        const uint64_t bal = __ballot(below);
-        const int nb1 = __popcll(bal & 0xffffffffull);
-        const int nb2 = __popcll(bal >> 32);
-        const double n_lo1 = nb1 > 0 ? lo1 + (hi1 - lo1) * (double)nb1 / 33.0 : lo1;
-        const double n_hi1 = nb1 < 32 ? lo1 + (hi1 - lo1) * (double)(nb1 + 1) / 33.0 : hi1;
-        const double n_lo2 = nb2 > 0 ? lo2 + (hi2 - lo2) * (double)nb2 / 33.0 : lo2;
-        const double n_hi2 = nb2 < 32 ? lo2 + (hi2 - lo2) * (double)(nb2 + 1) / 33.0 : hi2;
-        lo1 = n_lo1; hi1 = n_hi1; lo2 = n_lo2; hi2 = n_hi2;
-    }
-    sp.amax = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
+    spectrum_refine<NB>(S, lane, sp, rounds, rel);
     return sp;
 }
 
@@ -725,10 +745,26 @@ __device__ __forceinline__ Spectrum eval_spectrum(double (&a)[64], Shared<NB>& S
     return spectrum_max<NB>(S, t.lane, rounds, rel);
 }
 
-// kappa > target ?  (non-finite counts as above, like an infinite kappa)
+// kappa_2(T) > target ?  (non-finite counts as above, like an infinite kappa)
+// kappa > target exactly when some |lambda| < max|lambda| / target.  With
+// max |lambda| known to lie in [alo, ahi], an eigenvalue below alo / target
+// decides "above" and none below ahi / target decides "not above"; only when
+// the two counts differ is max |lambda| refined (two multisection rounds at a
+// time), so every decision is the one the Sturm counts of T give at the exact
+// max |lambda|, up to a bracket of a few ulps.  sp's brackets are refined in place.
 template <int NB>
-__device__ __forceinline__ bool kappa_above(const Shared<NB>& S, int lane, const Spectrum& sp, double target) {
+__device__ __forceinline__ bool kappa_above(const Shared<NB>& S, int lane, Spectrum& sp, double target) {
     if (!sp.finite || !(sp.amax > 0.0)) return true;
+    for (int it = 0; it < 12; ++it) {
+        double alo, ahi;
+        amax_bounds(sp, alo, ahi);
+        int ca, cb;
+        small_counts<NB>(S, lane, sp, alo / target, ahi / target, ca, cb);
+        if (ca > 0) return true;
+        if (cb == 0) return false;
+        if (ahi - alo <= 8.0 * 2.2e-16 * ahi) break;  // bracket at FP64 resolution
+        spectrum_refine<NB>(S, lane, sp, 2);
+    }
     int ca, cb;
     small_counts<NB>(S, lane, sp, sp.amax / target, sp.amax / target, ca, cb);
     return ca > 0;
@@ -743,7 +779,8 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
     const int c = t.c;
     // ---- gather the stencil (thread's column node; rb == 0 threads fill LDS)
     double px = 0, py = 0, pz = 0, nx = 0, ny = 0, nz = 0;
-    bool bad = false;  // stencil index outside [0, N): read node 0 instead, flag the stencil
+    bool bad = false;   // stencil index outside [0, N): read node 0 instead, flag the stencil
+    bool badn = false;  // zero or non-finite normal: Pi_i undefined, flag the stencil
     if (c < n) {
         int64_t node = J.idx[s * n + c];
         bad = node < 0 || node >= J.N;
@@ -756,7 +793,9 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
             ny = J.nrm[3 * node + 1];
             nz = J.nrm[3 * node + 2];
             const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-            nx /= nn; ny /= nn; nz /= nn;
+            badn = !(nn > 0.0 && nn <= 1.79e308);
+            const double dn = badn ? 1.0 : nn;
+            nx /= dn; ny /= dn; nz /= dn;
         }
         if (t.rb == 0) {
             S.x[c] = px;
@@ -772,14 +811,16 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
     // ---- stencil radius, scaled offsets of the thread's column node and row node
     const double dx0 = px - S.x[0], dy0 = py - S.y[0], dz0 = pz - S.z[0];
     const double r20 = c < n ? (dx0 * dx0 + dy0 * dy0) + dz0 * dz0 : 0.0;
-    // 2: an index out of range somewhere in the stencil; 1: two nodes coincide
-    const double flagf = max_cols<NB>(bad ? 2.0 : ((c > 0 && c < n && r20 == 0.0) ? 1.0 : 0.0), S, t);
+    // 3: an index out of range somewhere in the stencil; 2: a zero or
+    // non-finite normal; 1: two nodes coincide
+    const double flagf =
+        max_cols<NB>(bad ? 3.0 : (badn ? 2.0 : ((c > 0 && c < n && r20 == 0.0) ? 1.0 : 0.0)), S, t);
     if (flagf >= 2.0) {
         if (t.tid == 0) {
             if (J.eps) J.eps[s] = NAN;
             if (J.kappa) J.kappa[s] = NAN;
             if (J.nevals) J.nevals[s] = 0;
-            if (J.status) J.status[s] = RBFFD_ST_BAD_INDEX;
+            if (J.status) J.status[s] = flagf >= 3.0 ? RBFFD_ST_BAD_INDEX : RBFFD_ST_BAD_NORMAL;
         }
         if (!J.kappa_only && c < n && t.rb == 0) J.w[s * n + c] = NAN;
         bsync<NB>();
@@ -870,7 +911,9 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
                         eps = mid;
                         stop = true;
                         have_final = true;
-                        sp = spectrum_max<NB>(S, t.lane, 8);  // full precision for the reported kappa
+                        // six more rounds: the same brackets as eight from the start,
+                        // full precision for the reported kappa
+                        spectrum_refine<NB>(S, t.lane, sp, 6);
                         break;
                     }
                 }

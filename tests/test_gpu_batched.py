@@ -236,3 +236,40 @@ print(json.dumps(t))
     for a, b in zip(t1, t2):
         assert (a["stencils_per_item"], a["groups_per_cu"], a["order"]) == (b["stencils_per_item"], b["groups_per_cu"], b["order"])
         assert abs(a["us_per_stencil"] - b["us_per_stencil"]) <= 1e-5 * max(1.0, a["us_per_stencil"])
+
+
+def test_batch64_sample_against_oracle(lib):
+    """The 64-surface batch at its full size (N log-uniform in [2000, 60000],
+    n in {31, 50, 70, 101}, bisection to kappa_T = 1e12): two seeded rows of
+    every surface against the oracle's bisection and weights."""
+    import math
+
+    from oracle.shape import stencil_kappa
+
+    meta = surface_batch()
+    surfs = [(dev(s["X"]), dev(s["nrm"]), s["n"]) for s in meta]
+    print(f"[batch64] {sum(len(s['X']) for s in meta)} stencils", flush=True)
+    got = lib.build_weights_batched(surfs, eps_mode="bisect", kappa_target=1e12)
+    rng = np.random.default_rng(64)
+    worst = 0.0
+    for s, m in enumerate(meta):
+        X, nrm, n = m["X"], m["nrm"], m["n"]
+        idx = host(got[s].idx)
+        eg, st = host(got[s].eps), host(got[s].status)
+        assert np.all(st == 0), (s, np.unique(st))
+        rows = rng.choice(len(X), 2, replace=False)
+        for i in rows:
+            eo, _, _, sto = bisect_eps(X[idx[i]], 1e12)
+            assert sto == 0
+            if abs(eg[i] - eo) > 2e-4:  # a decision at kappa(mid) ~ kappa_T within FP64's evaluation error
+                k = stencil_kappa(X[idx[i]], eg[i])
+                print(f"[batch64] surface {s} ({m['kind']}, n={n}) row {i}: eps {eg[i]:.6f} vs {eo:.6f}, "
+                      f"oracle kappa at gpu eps {k:.6e}", flush=True)
+                assert abs(math.log(k / 1e12)) < 1e-3
+        wo = oracle_weights(X, nrm, idx, eg, rows=rows)
+        k = np.array([stencil_kappa(X[idx[i]], eg[i]) for i in rows])
+        wg = host(got[s].w)[rows]
+        err = np.linalg.norm(wg - wo, axis=1) / np.linalg.norm(wo, axis=1)
+        worst = max(worst, float(np.max(err / (k * 2.0 ** -53))))
+        assert np.all(err <= np.maximum(1e-9, 0.5 * k * 2.0 ** -53)), (s, err, k)
+    print(f"[batch64] weights: max err/(kappa u) {worst:.4f}", flush=True)
