@@ -123,7 +123,7 @@ def _pool_init(X, nrm):
     _POOL_X, _POOL_NRM = X, nrm
 
 
-def _pool_ready():
+def _pool_ready(_):
     return os.getpid()
 
 

@@ -263,6 +263,22 @@ int rbffd_op_stats(rbffd_op op, int64_t* nslices, int64_t* halo_slices, int64_t*
 int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const double* u, double* Lu);
 
 /*
+ * rbffd_apply without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results (bit for bit)
+ * as rbffd_apply; the two internal-order vectors (2 x padded rows x 8 bytes
+ * in FP64, x 4 bytes in FP32) live in one fixed device array of
+ * RBFFD_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends, instead of
+ * the operator's workspace.  Every call on one GPU uses that GPU's array:
+ * calls that overlap on one GPU (two streams, two threads) race and must be
+ * ordered by the caller.  Nothing in the array needs to start at zero.
+ * Errors: as rbffd_apply; RBFFD_E_UNSUPPORTED when the operator needs more
+ * than the array holds (FP64: more than 4,194,304 padded rows).
+ */
+#define RBFFD_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int rbffd_apply_noalloc(rbffd_ctx ctx, rbffd_op op, int32_t prec, const double* u, double* Lu);
+
+/*
  * Method of lines (Sec. 4.2, eq. kernel_mol) with classical RK4:
  * du_s/dt = D[s] L_X u_s + R_s(u).  state: nspecies x N FP64, caller order,
  * read and overwritten with the state after nsteps steps.  D: nspecies

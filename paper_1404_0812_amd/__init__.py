@@ -22,6 +22,7 @@ EPS_MODES = {"fixed": 0, "given": 1, "bisect": 2, "learned": 3}
 REACTIONS = {"none": 0, "schnakenberg": 1, "turing": 2}
 PRECS = {"f64": 0, "f32": 1}
 
+RBFFD_E_ARG, RBFFD_E_HIP, RBFFD_E_NOMEM, RBFFD_E_UNSUPPORTED, RBFFD_E_NONFINITE = -1, -2, -3, -4, -5
 ST_OK, ST_FALLBACK, ST_NO_BRACKET, ST_NONFINITE, ST_SINGULAR, ST_DUPLICATE, ST_BAD_INDEX, ST_BAD_NORMAL = range(8)
 
 

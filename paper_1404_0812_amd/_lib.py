@@ -110,6 +110,7 @@ SIGNATURES = {
     "rbffd_autotune_batched": (c_int32, [c_void_p, c_int32, ctypes.POINTER(Surface), ctypes.POINTER(WeightOpts),
                                          ctypes.c_char_p, c_int32, ctypes.POINTER(BatchTuning)]),
     "rbffd_apply": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
+    "rbffd_apply_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rbffd_step": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double), c_int32,
                              ctypes.POINTER(c_double), c_double, c_int64, c_int32]),
     "rbffd_step_forced": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double),

@@ -67,6 +67,9 @@ struct rbffd_op_s {
 };
 
 int set_error(rbffd_ctx ctx, int code, const char* fmt, ...);
+// Look up the device address of the allocation-free call's array on `device`
+// (current); once per device, at context creation.
+int noalloc_scratch_setup(rbffd_ctx ctx, int device);
 // Ensure ctx->scratch holds at least `bytes`; returns 0 or an error code.
 int ensure_scratch(rbffd_ctx ctx, size_t bytes);
 

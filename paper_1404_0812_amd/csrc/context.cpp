@@ -61,6 +61,10 @@ extern "C" int rbffd_create(rbffd_ctx* out, void* stream) {
         delete c;
         return RBFFD_E_HIP;
     }
+    if (noalloc_scratch_setup(c, c->device) != RBFFD_OK) {
+        delete c;
+        return RBFFD_E_HIP;
+    }
     *out = c;
     return RBFFD_OK;
 }

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -803,6 +804,72 @@ extern "C" int rbffd_op_stats(rbffd_op op, int64_t* nslices, int64_t* halo_slice
     if (halo_slices) *halo_slices = hs;
     if (halo_rows) *halo_rows = hr;
     if (halo_entries) *halo_entries = he;
+    return RBFFD_OK;
+}
+
+// ------------------------------------------------------------------------
+// Allocation-free operator application.  The internal-order input and output
+// vectors live in one fixed device array per GPU (RBFFD_NOALLOC_SCRATCH_BYTES),
+// whose device address is looked up once per device when a context is
+// created there.  The array's name is a host-side stand-in in host code: only
+// the looked-up pointer is ever passed to kernels.
+static __device__ __align__(256) unsigned char scratch[RBFFD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// Called by rbffd_create with `device` current.
+int noalloc_scratch_setup(rbffd_ctx ctx, int device) {
+    if (device < 0 || device >= MAX_DEVICES) return set_error(ctx, RBFFD_E_UNSUPPORTED, "device index %d", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return RBFFD_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return set_error(ctx, RBFFD_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
+    return RBFFD_OK;
+}
+
+extern "C" int rbffd_apply_noalloc(rbffd_ctx ctx, rbffd_op op, int32_t prec, const double* u, double* Lu) {
+    if (!ctx || !op || !u || !Lu) return set_error(ctx, RBFFD_E_ARG, "null argument");
+    if (prec != RBFFD_F64 && prec != RBFFD_F32) return set_error(ctx, RBFFD_E_ARG, "prec must be F64 or F32");
+    const int64_t N = op->N, P = op->P;
+    const size_t need = 2 * (size_t)P * (prec == RBFFD_F64 ? sizeof(double) : sizeof(float));
+    if (need > (size_t)RBFFD_NOALLOC_SCRATCH_BYTES)
+        return set_error(ctx, RBFFD_E_UNSUPPORTED, "operator of %lld padded rows needs %zu bytes of scratch, above the "
+                         "%d-byte array of the allocation-free call", (long long)P, need, RBFFD_NOALLOC_SCRATCH_BYTES);
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (ctx->device >= 0 && ctx->device < MAX_DEVICES) base = g_scratch_ptr[ctx->device];
+    }
+    if (!base) return set_error(ctx, RBFFD_E_HIP, "no scratch address for device %d", ctx->device);
+    hipStream_t st = ctx->stream;
+    const dim3 g((unsigned)((P + BLK - 1) / BLK)), b(BLK);
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nslices = op->nslices;
+    a.slices = op->slices;
+    a.lidx = op->lidx;
+    a.halo = op->halo;
+    if (prec == RBFFD_F64) {
+        double* Y = (double*)base;
+        double* out = Y + P;
+        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, 1, u, op->perm, Y);
+        hipLaunchKernelGGL(k_apply<double>, stage_grid(a.nslices), b, 0, st, a, op->idx64, op->w64, Y, out);
+        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, P, N, 1, out, op->perm, Lu);
+    } else {
+        float* Y = (float*)base;
+        float* out = Y + P;
+        hipLaunchKernelGGL(k_load_state<float>, g, b, 0, st, P, N, 1, u, op->perm, Y);
+        hipLaunchKernelGGL(k_apply<float>, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w32, Y, out);
+        hipLaunchKernelGGL(k_store_state<float>, g, b, 0, st, P, N, 1, out, op->perm, Lu);
+    }
+    HIP_TRY(ctx, hipGetLastError());
     return RBFFD_OK;
 }
 
