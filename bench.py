@@ -39,6 +39,18 @@ def weights_flops(n, r, evals):
     return evals * (4.0 / 3.0 * m ** 3 + 10.0 * n * n) + 30.0 * m * m + 40.0 * n * n
 
 
+def rk4_bytes_per_step_f64(N, n, stats=None, species=2):
+    """The same for FP64 state: per stage and row the n-1 off-diagonal FP64
+    weights with their 2-byte halo positions (4-byte indices outside staged
+    slices), the 8-byte diagonal weight, 4 bytes per halo-list entry, and the
+    species values: 16/40/40/32 B for two FP64 species over the four stages
+    (no compensation term)."""
+    hr, he = (stats[2], stats[3]) if stats else (0, 0)
+    mat = hr * (n - 1) * (8 + 2) + (N - hr) * (n - 1) * (8 + 4) + he * 4 + N * 8
+    vec = N * species * 8 * (3 + 5 + 5 + 4)
+    return 4 * mat + vec
+
+
 def rk4_bytes_per_step(N, n, stats=None, species=2):
     """Algorithmic HBM bytes of one FP32 RK4 step (4 stage kernels).  Each
     stage streams, per row, the n-1 off-diagonal FP32 weights and their column
@@ -439,8 +451,14 @@ def run_bench(args, torch, X, nrm, pool):
             fin = out.cpu().numpy()
             # FP32 state against an FP64 run of the same steps (untimed); FP64 on
             # this path matches the oracle to 1e-12 in the tests
-            ref64 = op.step(state0, dt_rk4, args.rk4_steps, prec="f64", D=DIFF, reaction="schnakenberg",
-                            params=SCHNAK, graph_steps=100).cpu().numpy()
+            torch.cuda.synchronize()
+            a64 = ev()
+            ref64_t = op.step(state0, dt_rk4, args.rk4_steps, prec="f64", D=DIFF, reaction="schnakenberg",
+                              params=SCHNAK, graph_steps=100)
+            b64 = ev()
+            torch.cuda.synchronize()
+            ms_rk4_f64 = a64.elapsed_time(b64) / args.rk4_steps
+            ref64 = ref64_t.cpu().numpy()
             fp32_vs_fp64 = float(np.linalg.norm(fin - ref64) / np.linalg.norm(ref64))
             print(f"[bench] FP32 vs FP64 state after {args.rk4_steps} steps: {fp32_vs_fp64:.3e}", flush=True)
         del op
@@ -547,6 +565,10 @@ def run_bench(args, torch, X, nrm, pool):
         "warmup": args.warmup,
         "ms_per_step": sum(med[k] for k in ("knn", "predict", "weights", "op", "rk4")),
         "ms_per_rk4_step": ms_rk4,
+        "rk4_f64": {"ms_per_step": ms_rk4_f64,
+                    "algorithmic_bytes_per_step": rk4_bytes_per_step_f64(args.N, n, op_stats),
+                    "achieved_GBs": rk4_bytes_per_step_f64(args.N, n, op_stats) / (ms_rk4_f64 / 1e3) / 1e9,
+                    "frac_of_8TBs_at_2.67GB_per_step": 2.67e9 / (ms_rk4_f64 / 1e3) / 1e9 / HBM_PEAK_GBS},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

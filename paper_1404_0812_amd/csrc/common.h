@@ -24,15 +24,14 @@ struct rbffd_ctx_s {
 
 // One slice of the operator: 64 consecutive internal rows of one surface.
 struct OpSlice {
-    int64_t off64;  // element offset of the slice's slot 0 in the FP64 arrays (n slots)
-    int64_t off32;  // element offset in the FP32 off-diagonal arrays (n - 1 slots)
+    int64_t off32;  // element offset of the slice in the off-diagonal arrays (n - 1 slots)
     int32_t n;      // stencil size of the slice's rows
     int32_t rows;   // rows in use (64 except at a surface's end)
-    int32_t halo;   // FP32 path: distinct neighbour rows of the slice (<= OP_HALO_MAX), -1: too many
+    int32_t halo;   // distinct neighbour rows of the slice (<= OP_HALO_MAX), -1: too many
     int32_t pad;
 };
 
-// Largest slice neighbourhood staged in LDS by the FP32 stage kernels.
+// Largest slice neighbourhood staged in LDS by the stage kernels.
 constexpr int OP_HALO_MAX = 640;
 
 struct rbffd_op_s {
@@ -43,12 +42,12 @@ struct rbffd_op_s {
     int32_t nsurf = 0;
     int64_t nslices = 0;
     OpSlice* slices = nullptr;    // device, nslices
-    int32_t* idx64 = nullptr;     // FP64 form: slot k of row (slice, r) at off64 + 64 k + r, slot 0 = centre
-    double* w64 = nullptr;
-    int32_t* idx32 = nullptr;     // FP32 difference form: off-diagonal slots 1..n-1 at off32 + 64 (k-1) + r
-    float* w32 = nullptr;
-    uint16_t* lidx = nullptr;     // FP32 path: slot entries as positions in the slice's halo list
-    int32_t* halo = nullptr;      // FP32 path: OP_HALO_MAX sorted distinct neighbour rows per slice
+    double* wd64 = nullptr;       // FP64 diagonal weight of every internal row (P)
+    int32_t* idx32 = nullptr;     // off-diagonal slots 1..n-1 of row (slice, r) at off32 + slot_pos(k-1, n-1, r)
+    double* w64 = nullptr;        // FP64 weights of those slots
+    float* w32 = nullptr;         // FP32 weights of those slots (difference form)
+    uint16_t* lidx = nullptr;     // slot entries as positions in the slice's halo list
+    int32_t* halo = nullptr;      // OP_HALO_MAX sorted distinct neighbour rows per slice
     int32_t* perm = nullptr;      // internal row -> caller row (-1 for padding), P entries
     // state workspace (internal order), allocated on first step
     void* work = nullptr;

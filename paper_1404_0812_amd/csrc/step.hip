@@ -9,10 +9,14 @@
 // spatial order, so the gathered neighbour values are close in memory.  Many
 // surfaces (each with its own N and n) form one block-diagonal operator:
 // each surface starts on a fresh slice and each slice carries its own n.
-// FP64 state uses the plain form sum_j w_ij u_j over all n slots.  FP32 state
-// uses the difference form sum_{j != i} w_ij (u_j - u_i) with FP32 weights;
-// it equals L u because the rows of L_X sum to zero (constants are
-// reproduced), and it keeps L 1 = 0 exact in FP32.
+// Both precisions store the n - 1 off-diagonal slots of every row in the same
+// layout (FP32 and FP64 weights side by side, one index array) and read the
+// neighbour values through the slice's halo staged in LDS.  FP64 state uses
+// the plain form w_ii u_i + sum_{j != i} w_ij u_j (the diagonal weight kept
+// per row), exact for any weights.  FP32 state uses the difference form
+// sum_{j != i} w_ij (u_j - u_i) with FP32 weights; it equals L u because the
+// rows of L_X sum to zero (constants are reproduced), and it keeps L 1 = 0
+// exact in FP32.
 //
 // One RK4 stage is one kernel: it applies L to the stage input of every
 // species with one read of the row, adds the reaction, and writes the next
@@ -59,7 +63,7 @@ __global__ void k_inverse_perm(int64_t N, const int32_t* __restrict__ perm, int3
 __global__ void k_build_sell(int64_t N, int n, int64_t row0, int64_t col0, const int32_t* __restrict__ idx,
                              const double* __restrict__ w, const int32_t* __restrict__ perm,
                              const int32_t* __restrict__ iperm, const OpSlice* __restrict__ slices,
-                             int32_t* __restrict__ idx64, double* __restrict__ w64, int32_t* __restrict__ idx32,
+                             double* __restrict__ wd64, double* __restrict__ w64, int32_t* __restrict__ idx32,
                              float* __restrict__ w32, int32_t* __restrict__ gperm, int* __restrict__ bad) {
     int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= N) return;
@@ -80,13 +84,13 @@ __global__ void k_build_sell(int64_t N, int n, int64_t row0, int64_t col0, const
         if (!ok) *bad = 1;
         const int32_t j = (int32_t)(row0 + (ok ? ip : p));
         const double wk = ok ? w[i * n + k] : 0.0;
-        const int64_t q64 = sl.off64 + slot_pos(k, n, r);
-        idx64[q64] = j;
-        w64[q64] = wk;
-        if (k > 0) {
+        if (k == 0) {
+            wd64[q] = wk;
+        } else {
             const int64_t q32 = sl.off32 + slot_pos(k - 1, n - 1, r);
             idx32[q32] = j;
             w32[q32] = (float)wk;
+            w64[q32] = wk;
         }
     }
     gperm[q] = (int32_t)(col0 + i);
@@ -220,8 +224,9 @@ __device__ __forceinline__ void reaction(const T (&y)[2], T (&r)[2], const React
 struct StageArgs {
     int64_t nslices;
     const OpSlice* slices;
-    const uint16_t* lidx;   // FP32 path: halo positions of the slot entries
-    const int32_t* halo;    // FP32 path: halo lists (OP_HALO_MAX per slice)
+    const uint16_t* lidx;   // halo positions of the slot entries
+    const int32_t* halo;    // halo lists (OP_HALO_MAX per slice)
+    const double* wd64;     // FP64 path: diagonal weight per internal row
     double D[2];
     double dt;
     ReactParams rp;
@@ -281,10 +286,10 @@ __device__ __forceinline__ void vstore(T* __restrict__ Y, int64_t j, const T (&v
 struct RowPos {
     int64_t p;      // internal row
     int64_t slice;  // -1: past the last slice (the whole wavefront)
-    int64_t base;   // element offset of the slice (precision's array)
+    int64_t base;   // element offset of the slice's off-diagonal slots
     int lane;
     int ns;         // slots to read
-    int halo;       // FP32: halo size, or -1 (direct gathers)
+    int halo;       // halo size, or -1 (direct gathers)
     bool live;
 };
 
@@ -301,12 +306,11 @@ __device__ __forceinline__ RowPos row_pos(const StageArgs& a) {
     rp.slice = -1;
     if (slice >= a.nslices) return rp;
     const OpSlice sl = a.slices[slice];
-    constexpr bool f32 = sizeof(T) == 4;
     rp.slice = slice;
     rp.live = rp.lane < sl.rows;
-    rp.base = f32 ? sl.off32 : sl.off64;
-    rp.ns = f32 ? sl.n - 1 : sl.n;
-    rp.halo = f32 ? sl.halo : -1;
+    rp.base = sl.off32;
+    rp.ns = sl.n - 1;
+    rp.halo = sl.halo;
     return rp;
 }
 
@@ -343,17 +347,18 @@ __device__ __forceinline__ void accumulate(const T* __restrict__ Y, int j, T wk,
     }
 }
 
-// L applied to the stage input of row rp.p, in slot order.  FP32: difference
-// form over the n-1 off-diagonal slots; FP64: plain form over all n slots.
+// L applied to the stage input of row rp.p by direct gathers, in slot order.
+// FP32: difference form over the n-1 off-diagonal slots; FP64: the diagonal
+// term wd u_i, then the off-diagonal slots (plain form).
 template <typename T, int S>
 __device__ __forceinline__ void apply_row(const RowPos& rp, const int32_t* __restrict__ idx,
                                           const T* __restrict__ w, const T* __restrict__ Y, const T (&yi)[2],
-                                          T (&acc)[2]) {
+                                          T wd, T (&acc)[2]) {
     const int ns = rp.ns;
     const int G = ns >> 2;
     const int32_t* ix = idx + rp.base + 4 * rp.lane;
     const T* wx = w + rp.base + 4 * rp.lane;
-    T s0 = 0, s1 = 0;
+    T s0 = wd * yi[0], s1 = wd * yi[1];
     int g = 0;
     for (; g + 2 <= G; g += 2) {  // eight slots in flight
         int j[8];
@@ -383,94 +388,115 @@ __device__ __forceinline__ void apply_row(const RowPos& rp, const int32_t* __res
 typedef unsigned short u4v __attribute__((ext_vector_type(4)));
 
 // Stage the slice's halo values (all 64 lanes of the wavefront take part).
-template <int S>
+template <typename T, int S>
 __device__ __forceinline__ void load_halo(const RowPos& rp, const int32_t* __restrict__ halo,
-                                          const float* __restrict__ Y, typename Vec<float, S>::type* ylds) {
+                                          const T* __restrict__ Y, typename Vec<T, S>::type* ylds) {
     const int32_t* h = halo + rp.slice * OP_HALO_MAX;
-    for (int t = rp.lane; t < rp.halo; t += 64) ylds[t] = reinterpret_cast<const typename Vec<float, S>::type*>(Y)[h[t]];
+    for (int t = rp.lane; t < rp.halo; t += 64) ylds[t] = reinterpret_cast<const typename Vec<T, S>::type*>(Y)[h[t]];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int S>
-__device__ __forceinline__ void halo_value(const typename Vec<float, S>::type* ylds, int l, float (&y)[2]) {
+template <typename T, int S>
+__device__ __forceinline__ void halo_value(const typename Vec<T, S>::type* ylds, int l, T (&y)[2]) {
     if constexpr (S == 2) {
-        const float2 v = ylds[l];
+        const typename Vec<T, 2>::type v = ylds[l];
         y[0] = v.x;
         y[1] = v.y;
     } else {
         y[0] = ylds[l];
-        y[1] = 0.0f;
+        y[1] = (T)0;
     }
 }
 
-// FP32 difference form over the n-1 off-diagonal slots, neighbour values from
-// the staged halo (same slot order as apply_row).
-template <int S>
+// four consecutive weights of one lane
+__device__ __forceinline__ void loadw4(const float* wx, float (&w)[4]) {
+    const f4v wv = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(wx));
+    w[0] = wv.x; w[1] = wv.y; w[2] = wv.z; w[3] = wv.w;
+}
+__device__ __forceinline__ void loadw4(const double* wx, double (&w)[4]) {
+    const d2v w0 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(wx));
+    const d2v w1 = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(wx) + 1);
+    w[0] = w0.x; w[1] = w0.y; w[2] = w1.x; w[3] = w1.y;
+}
+
+// The n-1 off-diagonal slots with neighbour values from the staged halo (same
+// slot order as apply_row): FP32 difference form, FP64 plain form after the
+// diagonal term.
+template <typename T, int S>
 __device__ __forceinline__ void apply_row_halo(const RowPos& rp, const uint16_t* __restrict__ lidx,
-                                               const float* __restrict__ w, const typename Vec<float, S>::type* ylds,
-                                               const float (&yi)[2], float (&acc)[2]) {
+                                               const T* __restrict__ w, const typename Vec<T, S>::type* ylds,
+                                               const T (&yi)[2], T wd, T (&acc)[2]) {
+    constexpr bool diff = sizeof(T) == 4;
     const int ns = rp.ns;
     const int G = ns >> 2;
     const uint16_t* lx = lidx + rp.base + 4 * rp.lane;
-    const float* wx = w + rp.base + 4 * rp.lane;
-    float s0 = 0.0f, s1 = 0.0f;
-    auto acc1 = [&](int l, float wk) {
-        float y[2];
-        halo_value<S>(ylds, l, y);
-        s0 = fma(wk, y[0] - yi[0], s0);
-        if (S == 2) s1 = fma(wk, y[1] - yi[1], s1);
+    const T* wx = w + rp.base + 4 * rp.lane;
+    T s0 = wd * yi[0], s1 = wd * yi[1];
+    auto acc1 = [&](int l, T wk) {
+        T y[2];
+        halo_value<T, S>(ylds, l, y);
+        if (diff) {
+            s0 = fma(wk, y[0] - yi[0], s0);
+            if (S == 2) s1 = fma(wk, y[1] - yi[1], s1);
+        } else {
+            s0 = fma(wk, y[0], s0);
+            if (S == 2) s1 = fma(wk, y[1], s1);
+        }
     };
     int g = 0;
     for (; g + 4 <= G; g += 4) {  // sixteen slots in flight
         u4v lv[4];
-        f4v wv[4];
+        T wv[4][4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             lv[q] = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(lx + 256 * (g + q)));
-            wv[q] = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(wx + 256 * (g + q)));
+            loadw4(wx + 256 * (g + q), wv[q]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            acc1(lv[q].x, wv[q].x);
-            acc1(lv[q].y, wv[q].y);
-            acc1(lv[q].z, wv[q].z);
-            acc1(lv[q].w, wv[q].w);
+            acc1(lv[q].x, wv[q][0]);
+            acc1(lv[q].y, wv[q][1]);
+            acc1(lv[q].z, wv[q][2]);
+            acc1(lv[q].w, wv[q][3]);
         }
     }
     for (; g < G; ++g) {
         const u4v lv = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(lx + 256 * g));
-        const f4v wv = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(wx + 256 * g));
-        acc1(lv.x, wv.x);
-        acc1(lv.y, wv.y);
-        acc1(lv.z, wv.z);
-        acc1(lv.w, wv.w);
+        T wv[4];
+        loadw4(wx + 256 * g, wv);
+        acc1(lv.x, wv[0]);
+        acc1(lv.y, wv[1]);
+        acc1(lv.z, wv[2]);
+        acc1(lv.w, wv[3]);
     }
     const uint16_t* lr = lidx + rp.base + 256 * G + rp.lane;
-    const float* wr = w + rp.base + 256 * G + rp.lane;
+    const T* wr = w + rp.base + 256 * G + rp.lane;
     for (int t = 0; t < ns - 4 * G; ++t) acc1(__builtin_nontemporal_load(lr + 64 * t), __builtin_nontemporal_load(wr + 64 * t));
     acc[0] = s0;
     acc[1] = s1;
 }
 
-// L applied to the stage input of row rp.p: FP32 through the staged halo when
-// the slice has one, otherwise (and in FP64) by direct gathers.  Every lane of
-// the wavefront must call this (the halo is loaded cooperatively).
+// L applied to the stage input of row rp.p: through the staged halo when the
+// slice has one, otherwise by direct gathers.  Every lane of the wavefront
+// must call this (the halo is loaded cooperatively).
 template <typename T, int S>
 __device__ __forceinline__ void laplacian_row(const StageArgs& a, const RowPos& rp, const int32_t* __restrict__ idx,
                                               const T* __restrict__ w, const T* __restrict__ Y, const T (&yi)[2],
                                               T (&lap)[2]) {
-    if constexpr (sizeof(T) == 4) {
-        __shared__ typename Vec<float, S>::type ylds[BLK / 64][OP_HALO_MAX];
-        if (rp.halo >= 0) {
-            auto* yl = ylds[threadIdx.x >> 6];
-            load_halo<S>(rp, a.halo, Y, yl);
-            if (rp.live) apply_row_halo<S>(rp, a.lidx, w, yl, yi, lap);
-            return;
-        }
+    __shared__ typename Vec<T, S>::type ylds[BLK / 64][OP_HALO_MAX];
+    T wd = (T)0;
+    if constexpr (sizeof(T) == 8) {
+        if (rp.live) wd = __builtin_nontemporal_load(a.wd64 + rp.p);
     }
-    if (rp.live) apply_row<T, S>(rp, idx, w, Y, yi, lap);
+    if (rp.halo >= 0) {
+        auto* yl = ylds[threadIdx.x >> 6];
+        load_halo<T, S>(rp, a.halo, Y, yl);
+        if (rp.live) apply_row_halo<T, S>(rp, a.lidx, w, yl, yi, wd, lap);
+        return;
+    }
+    if (rp.live) apply_row<T, S>(rp, idx, w, Y, yi, wd, lap);
 }
 
 // RK4 stage `ST` (0..3).  Y: stage input; U: state at the start of the step;
@@ -638,7 +664,7 @@ void reset_graph(rbffd_op op) {
 int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* out) {
     std::vector<OpSlice> sl;
     std::vector<int64_t> row0(nsurf), col0(nsurf);
-    int64_t P = 0, N = 0, off64 = 0, off32 = 0, maxN = 0;
+    int64_t P = 0, N = 0, off32 = 0, maxN = 0;
     int32_t nmax = 0;
     for (int s = 0; s < nsurf; ++s) {
         row0[s] = P;
@@ -647,14 +673,12 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
         const int n = surf[s].n;
         for (int64_t r = 0; r < Ns; r += 64) {
             OpSlice o;
-            o.off64 = off64;
             o.off32 = off32;
             o.n = n;
             o.rows = (int32_t)std::min<int64_t>(64, Ns - r);
             o.halo = -1;
             o.pad = 0;
             sl.push_back(o);
-            off64 += 64 * (int64_t)n;
             off32 += 64 * (int64_t)(n - 1);
         }
         P += (Ns + 63) / 64 * 64;
@@ -672,8 +696,8 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
     op->nsurf = nsurf;
     op->nslices = (int64_t)sl.size();
     bool ok = hipMalloc(&op->slices, std::max<size_t>(1, sl.size()) * sizeof(OpSlice)) == hipSuccess &&
-              hipMalloc(&op->idx64, std::max<int64_t>(1, off64) * sizeof(int32_t)) == hipSuccess &&
-              hipMalloc(&op->w64, std::max<int64_t>(1, off64) * sizeof(double)) == hipSuccess &&
+              hipMalloc(&op->wd64, std::max<int64_t>(1, P) * sizeof(double)) == hipSuccess &&
+              hipMalloc(&op->w64, std::max<int64_t>(1, off32) * sizeof(double)) == hipSuccess &&
               hipMalloc(&op->idx32, std::max<int64_t>(1, off32) * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&op->w32, std::max<int64_t>(1, off32) * sizeof(float)) == hipSuccess &&
               hipMalloc(&op->lidx, std::max<int64_t>(1, off32) * sizeof(uint16_t)) == hipSuccess &&
@@ -703,7 +727,7 @@ int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* 
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(k_inverse_perm, g, b, 0, st, Ns, surf[s].perm, iperm, bad);
         hipLaunchKernelGGL(k_build_sell, g, b, 0, st, Ns, surf[s].n, row0[s], col0[s], surf[s].idx, surf[s].w,
-                           surf[s].perm, iperm, op->slices, op->idx64, op->w64, op->idx32, op->w32, op->perm, bad);
+                           surf[s].perm, iperm, op->slices, op->wd64, op->w64, op->idx32, op->w32, op->perm, bad);
         e = hipGetLastError();
     }
     if (e == hipSuccess && !sl.empty()) {
@@ -771,7 +795,7 @@ extern "C" int rbffd_op_destroy(rbffd_op op) {
     if (op->ctx) (void)hipStreamSynchronize(op->ctx->stream);
     reset_graph(op);
     if (op->slices) (void)hipFree(op->slices);
-    if (op->idx64) (void)hipFree(op->idx64);
+    if (op->wd64) (void)hipFree(op->wd64);
     if (op->w64) (void)hipFree(op->w64);
     if (op->idx32) (void)hipFree(op->idx32);
     if (op->w32) (void)hipFree(op->w32);
@@ -856,11 +880,12 @@ extern "C" int rbffd_apply_noalloc(rbffd_ctx ctx, rbffd_op op, int32_t prec, con
     a.slices = op->slices;
     a.lidx = op->lidx;
     a.halo = op->halo;
+    a.wd64 = op->wd64;
     if (prec == RBFFD_F64) {
         double* Y = (double*)base;
         double* out = Y + P;
         hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, 1, u, op->perm, Y);
-        hipLaunchKernelGGL(k_apply<double>, stage_grid(a.nslices), b, 0, st, a, op->idx64, op->w64, Y, out);
+        hipLaunchKernelGGL(k_apply<double>, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, Y, out);
         hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, P, N, 1, out, op->perm, Lu);
     } else {
         float* Y = (float*)base;
@@ -888,11 +913,12 @@ extern "C" int rbffd_apply(rbffd_ctx ctx, rbffd_op op, int32_t prec, const doubl
     a.slices = op->slices;
     a.lidx = op->lidx;
     a.halo = op->halo;
+    a.wd64 = op->wd64;
     if (prec == RBFFD_F64) {
         double* Y = (double*)op->work;
         double* out = Y + P;
         hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, 1, u, op->perm, Y);
-        hipLaunchKernelGGL(k_apply<double>, stage_grid(a.nslices), b, 0, st, a, op->idx64, op->w64, Y, out);
+        hipLaunchKernelGGL(k_apply<double>, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, Y, out);
         hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, P, N, 1, out, op->perm, Lu);
     } else {
         float* Y = (float*)op->work;
@@ -934,6 +960,7 @@ int step_impl(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32
     a.slices = op->slices;
     a.lidx = op->lidx;
     a.halo = op->halo;
+    a.wd64 = op->wd64;
     a.D[0] = D[0];
     a.D[1] = nspecies == 2 ? D[1] : 0.0;
     a.dt = dt;
@@ -958,7 +985,7 @@ int step_impl(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32
         a.lam = lam;
         a.t0 = t0;
     }
-    const int32_t* idx = prec == RBFFD_F64 ? op->idx64 : op->idx32;
+    const int32_t* idx = op->idx32;
     const void* w = prec == RBFFD_F64 ? (const void*)op->w64 : (const void*)op->w32;
     // counters are cleared by a kernel (no memset node near the captured graph)
     hipLaunchKernelGGL(k_set_steps, dim3(1), dim3(1), 0, st, steps_done, nonfinite);
