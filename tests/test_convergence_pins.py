@@ -174,3 +174,66 @@ def test_forced_sphere_tracks_manufactured_harmonic():
     (v,) = rk4(L, [Y], [1.0], dt=1e-4, nsteps=500)
     e_free = np.linalg.norm(v - ex) / np.linalg.norm(ex)
     assert errs[0] < 1e-2 and errs[1] < 0.5 * errs[0] and e_free > 0.2, (errs, e_free)
+
+
+# ------------------------------------------------------------ IMEX BDF ----
+
+from oracle.stepper import BDF_COEFFS, imex_bdf  # noqa: E402
+
+
+def test_bdf_coefficients_are_consistent():
+    """Each BDF row annihilates polynomials of degree <= k on the unit grid
+    (order k) and each extrapolation row reproduces them at the new point."""
+    for k, (a, b) in BDF_COEFFS.items():
+        for p in range(k + 1):
+            # sum_j a_j (1 - j)^p = d/dt t^p at t = 1 (times dt = 1) = p
+            lhs = sum(a[j] * (1.0 - j) ** p for j in range(k + 1))
+            assert abs(lhs - (p if p > 0 else 0.0)) < 1e-12, (k, p)
+        for p in range(k):  # k past values extrapolate degree k - 1 exactly
+            ext = sum(b[j - 1] * (1.0 - j) ** p for j in range(1, k + 1))
+            assert abs(ext - 1.0) < 1e-12, (k, p)
+        # and not degree k (the row is not padded with spurious accuracy)
+        assert abs(sum(b[j - 1] * (1.0 - j) ** k for j in range(1, k + 1)) - 1.0) > 1e-3
+
+
+def _forced_exact(t, a=-3.0, lam=-5.0, F=2.0, u0=0.7, t0=0.3):
+    return math.exp(a * (t - t0)) * u0 + F * (math.exp(lam * t) - math.exp(a * (t - t0) + lam * t0)) / (lam - a)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3, 4])
+@pytest.mark.parametrize("start", ["exact", "lower"])
+def test_imex_bdf_order_on_forced_linear_ode(order, start):
+    """u' = a u + exp(lam t) F (diffusion-like implicit term, implicit forcing):
+    the global error at t0 + 1 falls as dt^order when the history comes from
+    the exact solution (as the paper starts BDF4).  Started with the lower
+    orders instead, the BDF1 first step's O(dt^2) error caps the order at 2."""
+    a, lam, F, u0, t0 = -3.0, -5.0, 2.0, 0.7, 0.3
+    L = assemble(np.array([[0]]), np.array([[a]]))
+    errs = []
+    for n in (40, 80, 160):
+        dt = 1.0 / n
+        hist = [[np.array([_forced_exact(t0 - j * dt)])] for j in range(1, order)] if start == "exact" else None
+        (u,) = imex_bdf(L, [np.array([u0])], [1.0], dt=dt, nsteps=n, order=order, t0=t0,
+                        forcing=(lam, [np.array([F])]), history=hist)
+        errs.append(abs(u[0] - _forced_exact(t0 + 1.0)))
+    rates = [math.log2(errs[j] / errs[j + 1]) for j in range(2)]
+    want = order if start == "exact" else min(order, 2)
+    assert min(rates) > want - 0.35, (order, errs, rates)
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_imex_bdf_order_on_explicit_reaction(order):
+    """u' = -u^2 (explicit, extrapolated reaction only): exact u = u0 / (1 + u0 t)."""
+    L = assemble(np.array([[0, 1]]), np.array([[0.0, 0.0]]), N=2)[:1, :1]
+    prm = None
+    errs = []
+    for n in (50, 100, 200):
+        dt = 1.0 / n
+        # the Schnakenberg kinetics with a = b = 0 and gamma = 1 give R_u = -u + u^2 v;
+        # with v = 0 frozen (R_v = -u^2 v = 0) this is u' = -u
+        (u, v) = imex_bdf(L, [np.array([0.8]), np.array([0.0])], [0.0, 0.0], "schnakenberg",
+                          {"a": 0.0, "b": 0.0, "gamma": 1.0}, dt=dt, nsteps=n, order=order)
+        errs.append(abs(u[0] - 0.8 * math.exp(-1.0)))
+        assert v[0] == 0.0
+    rates = [math.log2(errs[j] / errs[j + 1]) for j in range(2)]
+    assert min(rates) > order - 0.2, (order, errs, rates)
