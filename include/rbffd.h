@@ -44,6 +44,7 @@ typedef struct rbffd_op_s* rbffd_op;
 #define RBFFD_E_NOMEM (-3)    /* device allocation of library scratch failed */
 #define RBFFD_E_UNSUPPORTED (-4) /* valid request outside what this library implements */
 #define RBFFD_E_NONFINITE (-5) /* rbffd_step: the state became non-finite (NaN or Inf) */
+#define RBFFD_E_NOCONV (-6)    /* rbffd_step_imex: a linear solve missed its tolerance */
 
 /* radial kernels (Sec. 2) */
 #define RBFFD_KERNEL_MQ 0  /* sqrt(1 + (eps r)^2) */
@@ -311,6 +312,32 @@ int rbffd_step(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int3
 int rbffd_step_forced(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, int32_t prec,
                       const double* D, int32_t reaction, const double* params, double dt, int64_t nsteps,
                       int32_t graph_steps, double t0, const double* forcing, double lambda);
+
+/*
+ * Semi-implicit BDF time stepping (SBDF-k, the paper's BDF4 of Sec. 6 for
+ * diffusion and SBDF2 of Sec. 7 for reaction-diffusion), FP64:
+ *   sum_{j=0}^{k} a_j u^{n+1-j} = dt (D L_X u^{n+1} + f(t_{n+1}) + sum_{j=1}^{k} b_j R(u^{n+1-j}))
+ * with the k-step backward difference row a and the extrapolation row b of
+ * order k; the diffusion and the forcing f_s(t, x_i) = exp(lambda t)
+ * forcing[s * N + i] (nullable) are implicit, the reaction explicit.  Each
+ * step solves (I - gamma L_X) u_s = rhs_s, gamma = dt D_s / a_0, per species
+ * with BiCGSTAB (Jacobi preconditioner, initial guess u^n) to the relative
+ * residual tol (the paper: 1e-12), at most maxit iterations.
+ * state: nspecies x N FP64 at time t0, caller order, overwritten with the
+ * state after nsteps steps.  history (nullable): the states at t0 - dt,
+ * t0 - 2 dt, ..., (order - 1) x nspecies x N (the paper starts BDF4 from the
+ * exact solution); without it the first steps use orders 1, 2, ... (which
+ * limits the global order to 2).  iters_out, relres_out (HOST, nullable):
+ * total iterations and the largest final relative residual.  Synchronises
+ * the context's stream.
+ * Errors: as rbffd_step; order outside 1..4; tol <= 0; maxit < 1;
+ * RBFFD_E_NOCONV when a solve misses tol (state holds the steps done);
+ * RBFFD_E_NONFINITE when a residual is not finite.
+ */
+int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, const double* D, int32_t reaction,
+                    const double* params, double dt, int64_t nsteps, int32_t order, const double* history, double t0,
+                    const double* forcing, double lambda, double tol, int32_t maxit, int64_t* iters_out,
+                    double* relres_out);
 
 /* ------------------------------------------------------------------------
  * Learned shape parameter.  A 128 -> 128 -> 128 -> 1 ReLU network maps a

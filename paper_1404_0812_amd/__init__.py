@@ -22,7 +22,7 @@ EPS_MODES = {"fixed": 0, "given": 1, "bisect": 2, "learned": 3}
 REACTIONS = {"none": 0, "schnakenberg": 1, "turing": 2}
 PRECS = {"f64": 0, "f32": 1}
 
-RBFFD_E_ARG, RBFFD_E_HIP, RBFFD_E_NOMEM, RBFFD_E_UNSUPPORTED, RBFFD_E_NONFINITE = -1, -2, -3, -4, -5
+RBFFD_E_ARG, RBFFD_E_HIP, RBFFD_E_NOMEM, RBFFD_E_UNSUPPORTED, RBFFD_E_NONFINITE, RBFFD_E_NOCONV = -1, -2, -3, -4, -5, -6
 ST_OK, ST_FALLBACK, ST_NO_BRACKET, ST_NONFINITE, ST_SINGULAR, ST_DUPLICATE, ST_BAD_INDEX, ST_BAD_NORMAL = range(8)
 
 
@@ -370,6 +370,29 @@ class Operator:
         self.ctx.leave()
         self.ctx.check(rc)
         return st
+
+    def step_imex(self, state, dt, nsteps, order=2, D=(1.0,), reaction="none", params=(), history=None,
+                  forcing=None, t0=0.0, lam=0.0, tol=1e-12, maxit=200):
+        """Semi-implicit BDF steps (FP64).  history: (order-1) x S x N states at
+        t0 - dt, t0 - 2 dt, ... or None.  Returns (state, iterations, worst
+        relative residual)."""
+        st = _dev(state, torch.float64, "state").clone()
+        if st.dim() == 1:
+            st = st.unsqueeze(0)
+        S = st.shape[0]
+        Darr = (ctypes.c_double * max(2, len(D)))(*[float(x) for x in D])
+        prm = (ctypes.c_double * 5)(*([float(x) for x in params] + [0.0] * (5 - len(params))))
+        H = _dev(history, torch.float64, "history").contiguous() if history is not None else None
+        F = _dev(forcing, torch.float64, "forcing").reshape(st.shape) if forcing is not None else None
+        its = ctypes.c_int64()
+        res = ctypes.c_double()
+        self.ctx.enter(st, H, F)
+        rc = self.ctx.lib.rbffd_step_imex(self.ctx.h, self.h, S, _ptr(st), Darr, REACTIONS[reaction], prm, float(dt),
+                                          int(nsteps), int(order), _ptr(H), float(t0), _ptr(F), float(lam),
+                                          float(tol), int(maxit), ctypes.byref(its), ctypes.byref(res))
+        self.ctx.leave()
+        self.ctx.check(rc)
+        return st, its.value, res.value
 
 
 # ------------------------------------------------------------ learned eps ----

@@ -113,6 +113,9 @@ SIGNATURES = {
     "rbffd_apply_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]),
     "rbffd_step": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double), c_int32,
                              ctypes.POINTER(c_double), c_double, c_int64, c_int32]),
+    "rbffd_step_imex": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, ctypes.POINTER(c_double), c_int32,
+                                  ctypes.POINTER(c_double), c_double, c_int64, c_int32, c_void_p, c_double, c_void_p,
+                                  c_double, c_double, c_int32, ctypes.POINTER(c_int64), ctypes.POINTER(c_double)]),
     "rbffd_step_forced": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, ctypes.POINTER(c_double),
                                     c_int32, ctypes.POINTER(c_double), c_double, c_int64, c_int32, c_double,
                                     c_void_p, c_double]),

@@ -52,6 +52,9 @@ struct rbffd_op_s {
     // state workspace (internal order), allocated on first step
     void* work = nullptr;
     size_t work_bytes = 0;
+    // vectors of the implicit (BDF) stepper, allocated on first use
+    void* impl = nullptr;
+    size_t impl_bytes = 0;
     // captured graph cache
     hipGraphExec_t graph = nullptr;
     int graph_key_species = -1, graph_key_prec = -1, graph_key_react = -1, graph_key_steps = -1;

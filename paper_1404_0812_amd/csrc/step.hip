@@ -803,6 +803,7 @@ extern "C" int rbffd_op_destroy(rbffd_op op) {
     if (op->halo) (void)hipFree(op->halo);
     if (op->perm) (void)hipFree(op->perm);
     if (op->work) (void)hipFree(op->work);
+    if (op->impl) (void)hipFree(op->impl);
     if (op->counters) (void)hipFree(op->counters);
     if (op->nonfinite_host) (void)hipHostFree(op->nonfinite_host);
     delete op;
@@ -1082,4 +1083,439 @@ extern "C" int rbffd_step_forced(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, d
     if (!forcing) return set_error(ctx, RBFFD_E_ARG, "forcing is required");
     return step_impl(ctx, op, nspecies, state, prec, D, reaction, params, dt, nsteps, graph_steps, t0, forcing,
                      lambda);
+}
+
+// ------------------------------------------------------------------------
+// Semi-implicit BDF time stepping (the paper's BDF4 of Sec. 6 for the forced
+// diffusion problems and SBDF2 of Sec. 7 for the Turing system): each step
+//   sum_{j=0}^{k} a_j u^{n+1-j} = dt (D L u^{n+1} + f(t_{n+1}) + sum_{j=1}^{k} b_j R(u^{n+1-j})),
+// i.e. (I - gamma L) u_s^{n+1} = rhs_s / a_0 with gamma = dt D_s / a_0, solved
+// per species by BiCGSTAB with a Jacobi (diagonal) preconditioner.  Vectors
+// are FP64 in internal order, one array per species; every scalar of the
+// iteration stays on the device, the host reads the residual norm once per
+// iteration to stop.
+namespace {
+
+constexpr int RED_BLOCKS = 512;
+
+struct BdfCoef {
+    double a[5], b[4];
+};
+
+// k-step BDF row a and extrapolation row b (see the oracle's table).
+BdfCoef bdf_coef(int k) {
+    BdfCoef c;
+    std::memset(&c, 0, sizeof(c));
+    if (k == 1) {
+        c.a[0] = 1.0; c.a[1] = -1.0;
+        c.b[0] = 1.0;
+    } else if (k == 2) {
+        c.a[0] = 1.5; c.a[1] = -2.0; c.a[2] = 0.5;
+        c.b[0] = 2.0; c.b[1] = -1.0;
+    } else if (k == 3) {
+        c.a[0] = 11.0 / 6.0; c.a[1] = -3.0; c.a[2] = 1.5; c.a[3] = -1.0 / 3.0;
+        c.b[0] = 3.0; c.b[1] = -3.0; c.b[2] = 1.0;
+    } else {
+        c.a[0] = 25.0 / 12.0; c.a[1] = -4.0; c.a[2] = 3.0; c.a[3] = -4.0 / 3.0; c.a[4] = 0.25;
+        c.b[0] = 4.0; c.b[1] = -6.0; c.b[2] = 4.0; c.b[3] = -1.0;
+    }
+    return c;
+}
+
+// Scalars of one BiCGSTAB solve (device).
+struct KrylovScalars {
+    double rho, rho_old, alpha, omega, beta;
+    double bb, rr;        // ||b||^2, ||r||^2
+    int breakdown;
+};
+
+struct HistPtrs {
+    const double* u[4];   // u^n, u^{n-1}, ... (one species)
+    const double* r[4];   // R_s at those states (nullable entries when no reaction)
+};
+
+// b = (-sum_{j>=1} a_j u^{n+1-j} + dt sum_j b_j R^{n+1-j} + dt ef F) / a_0
+// (0 on padding rows, whose reaction values are not zero in general)
+__global__ void k_bdf_rhs(int64_t P, int k, BdfCoef c, HistPtrs h, const double* __restrict__ F, double ef,
+                          double dt, const int32_t* __restrict__ perm, double* __restrict__ out) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    if (perm[p] < 0) {
+        out[p] = 0.0;
+        return;
+    }
+    double v = 0.0;
+    for (int j = 1; j <= k; ++j) {
+        v = fma(-c.a[j], h.u[j - 1][p], v);
+        if (h.r[j - 1]) v = fma(dt * c.b[j - 1], h.r[j - 1][p], v);
+    }
+    if (F) v = fma(dt * ef, F[p], v);
+    out[p] = v / c.a[0];
+}
+
+// R(u) for both species of one state (rows in internal order, per-species arrays).
+template <int R>
+__global__ void k_reaction2(int64_t P, const double* __restrict__ u, const double* __restrict__ v, ReactParams rp,
+                            double* __restrict__ ru, double* __restrict__ rv) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double y[2] = {u[p], v[p]}, r[2];
+    reaction<double, R>(y, r, rp);
+    ru[p] = r[0];
+    rv[p] = r[1];
+}
+
+// Inverse of the diagonal of I - gamma L (0 on padding rows, which then stay 0).
+__global__ void k_inv_diag(int64_t P, const double* __restrict__ wd, const int32_t* __restrict__ perm, double gamma,
+                           double* __restrict__ invd) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    invd[p] = perm[p] >= 0 ? 1.0 / (1.0 - gamma * wd[p]) : 0.0;
+}
+
+// out = x - gamma L x (live rows; padding rows keep their zero)
+__global__ __launch_bounds__(BLK) void k_amul(StageArgs a, const int32_t* __restrict__ idx,
+                                              const double* __restrict__ w, const double* __restrict__ X,
+                                              double gamma, double* __restrict__ out) {
+    const RowPos rp = row_pos<double>(a);
+    if (rp.slice < 0) return;
+    double yi[2] = {0.0, 0.0};
+    if (rp.live) yi[0] = X[rp.p];
+    double lap[2];
+    laplacian_row<double, 1>(a, rp, idx, w, X, yi, lap);
+    if (rp.live) out[rp.p] = fma(-gamma, lap[0], yi[0]);
+}
+
+__device__ __forceinline__ double wave_sum_block(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block sums of up to two dot products over P rows; partials[blk * 2 + q].
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum_block(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+template <int NQ>
+__global__ __launch_bounds__(256) void k_dots(int64_t P, const double* __restrict__ a0, const double* __restrict__ b0,
+                                              const double* __restrict__ a1, const double* __restrict__ b1,
+                                              double* __restrict__ partials) {
+    __shared__ double sh[4];
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        s0 = fma(a0[p], b0[p], s0);
+        if (NQ == 2) s1 = fma(a1[p], b1[p], s1);
+    }
+    const double t0 = block_sum(s0, sh);
+    double t1 = 0.0;
+    if (NQ == 2) t1 = block_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        partials[2 * blockIdx.x] = t0;
+        partials[2 * blockIdx.x + 1] = t1;
+    }
+}
+
+// Sum the block partials in a fixed order (one wave): deterministic.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, double& d0, double& d1) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < RED_BLOCKS; i += 64) {
+        s0 += partials[2 * i];
+        s1 += partials[2 * i + 1];
+    }
+    d0 = wave_sum_block(s0);
+    d1 = wave_sum_block(s1);
+}
+
+// Scalar steps of the iteration (one wave each).
+// MODE 0: bb = d0, rr = d1, rho_old = alpha = omega = 1 (start)
+// MODE 1: rho = d0; beta = (rho / rho_old) (alpha / omega); rho_old = rho
+// MODE 2: alpha = rho / d0
+// MODE 3: omega = d0 / d1 (t.s / t.t)
+// MODE 4: rr = d0
+template <int MODE>
+__global__ void k_krylov_scalar(const double* __restrict__ partials, KrylovScalars* __restrict__ ks) {
+    double d0, d1;
+    sum_partials(partials, d0, d1);
+    if (threadIdx.x != 0) return;
+    if (MODE == 0) {
+        ks->bb = d0;
+        ks->rr = d1;
+        ks->rho_old = ks->alpha = ks->omega = 1.0;
+        ks->breakdown = 0;
+    } else if (MODE == 1) {
+        const double rho = d0;
+        if (rho == 0.0 || ks->omega == 0.0) ks->breakdown = 1;
+        ks->beta = ks->breakdown ? 0.0 : (rho / ks->rho_old) * (ks->alpha / ks->omega);
+        ks->rho = rho;
+        ks->rho_old = rho;
+    } else if (MODE == 2) {
+        if (d0 == 0.0) ks->breakdown = 1;
+        ks->alpha = ks->breakdown ? 0.0 : ks->rho / d0;
+    } else if (MODE == 3) {
+        ks->omega = d1 > 0.0 ? d0 / d1 : 0.0;
+    } else {
+        ks->rr = d0;
+    }
+}
+
+// r = b - Ax; rhat = r; p = v = 0
+__global__ void k_kry_init(int64_t P, const double* __restrict__ b, const double* __restrict__ ax,
+                           double* __restrict__ r, double* __restrict__ rh, double* __restrict__ pv,
+                           double* __restrict__ v) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double rv = b[p] - ax[p];
+    r[p] = rv;
+    rh[p] = rv;
+    pv[p] = 0.0;
+    v[p] = 0.0;
+}
+
+// p = r + beta (p - omega v); ph = M^-1 p
+__global__ void k_kry_p(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ r,
+                        double* __restrict__ pv, const double* __restrict__ v, const double* __restrict__ invd,
+                        double* __restrict__ ph) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double beta = ks->beta, omega = ks->omega;
+    const double np = fma(beta, fma(-omega, v[p], pv[p]), r[p]);
+    pv[p] = np;
+    ph[p] = invd[p] * np;
+}
+
+// s = r - alpha v; sh = M^-1 s
+__global__ void k_kry_s(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ r,
+                        const double* __restrict__ v, const double* __restrict__ invd, double* __restrict__ s,
+                        double* __restrict__ sh) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double sv = fma(-ks->alpha, v[p], r[p]);
+    s[p] = sv;
+    sh[p] = invd[p] * sv;
+}
+
+// x += alpha ph + omega sh; r = s - omega t
+__global__ void k_kry_xr(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ ph,
+                         const double* __restrict__ sh, const double* __restrict__ s, const double* __restrict__ t,
+                         double* __restrict__ x, double* __restrict__ r) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double alpha = ks->alpha, omega = ks->omega;
+    x[p] = fma(omega, sh[p], fma(alpha, ph[p], x[p]));
+    r[p] = fma(-omega, t[p], s[p]);
+}
+
+__global__ void k_copy(int64_t P, const double* __restrict__ src, double* __restrict__ dst) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p < P) dst[p] = src[p];
+}
+
+int ensure_impl(rbffd_op op, size_t bytes) {
+    if (op->impl_bytes >= bytes) return RBFFD_OK;
+    if (op->impl) {
+        (void)hipStreamSynchronize(op->ctx->stream);
+        (void)hipFree(op->impl);
+        op->impl = nullptr;
+        op->impl_bytes = 0;
+    }
+    if (hipMalloc(&op->impl, bytes) != hipSuccess) {
+        op->impl = nullptr;
+        return set_error(op->ctx, RBFFD_E_NOMEM, "cannot allocate %zu bytes for the implicit stepper", bytes);
+    }
+    op->impl_bytes = bytes;
+    // every vector starts at zero (padding rows are never written again)
+    HIP_TRY(op->ctx, hipMemsetAsync(op->impl, 0, bytes, op->ctx->stream));
+    return RBFFD_OK;
+}
+
+}  // namespace
+
+extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* state, const double* D,
+                               int32_t reaction, const double* params, double dt, int64_t nsteps, int32_t order,
+                               const double* history, double t0, const double* forcing, double lambda, double tol,
+                               int32_t maxit, int64_t* iters_out, double* relres_out) {
+    if (!ctx || !op || !state || !D) return set_error(ctx, RBFFD_E_ARG, "null argument");
+    if (nspecies != 1 && nspecies != 2) return set_error(ctx, RBFFD_E_ARG, "nspecies must be 1 or 2");
+    if (reaction < 0 || reaction > 2) return set_error(ctx, RBFFD_E_ARG, "unknown reaction %d", reaction);
+    if (reaction != RBFFD_REACT_NONE && nspecies != 2) return set_error(ctx, RBFFD_E_ARG, "reaction needs two species");
+    if (reaction != RBFFD_REACT_NONE && !params) return set_error(ctx, RBFFD_E_ARG, "reaction params required");
+    if (!(dt > 0.0)) return set_error(ctx, RBFFD_E_ARG, "dt must be > 0");
+    if (nsteps < 0) return set_error(ctx, RBFFD_E_ARG, "nsteps must be >= 0");
+    if (order < 1 || order > 4) return set_error(ctx, RBFFD_E_ARG, "order must be 1..4");
+    if (!(tol > 0.0) || maxit < 1) return set_error(ctx, RBFFD_E_ARG, "tol must be > 0 and maxit >= 1");
+    if (forcing && !(std::isfinite(t0) && std::isfinite(lambda)))
+        return set_error(ctx, RBFFD_E_ARG, "t0 and lambda must be finite");
+    op->ctx = ctx;
+    const int64_t N = op->N, P = op->P;
+    const int S = nspecies;
+    const bool react = reaction != RBFFD_REACT_NONE;
+    // layout: U[s][order], R[s][order] (reaction), F[s], invd, b, x, r, rh, p, ph, v, s, sh, t; partials; scalars
+    const int nvec = S * order * (react ? 2 : 1) + S + 11;
+    const size_t vbytes = (size_t)P * sizeof(double);
+    const size_t bytes = nvec * vbytes + 2 * RED_BLOCKS * sizeof(double) + 256;
+    int rc = ensure_impl(op, bytes);
+    if (rc) return rc;
+    hipStream_t st = ctx->stream;
+    double* base = (double*)op->impl;
+    auto vec = [&](int i) { return base + (size_t)i * P; };
+    int vi = 0;
+    double* U[2][4] = {};
+    double* Rh[2][4] = {};
+    for (int s = 0; s < S; ++s)
+        for (int j = 0; j < order; ++j) U[s][j] = vec(vi++);
+    if (react)
+        for (int s = 0; s < S; ++s)
+            for (int j = 0; j < order; ++j) Rh[s][j] = vec(vi++);
+    double* Fi[2] = {};
+    for (int s = 0; s < S; ++s) Fi[s] = vec(vi++);
+    double* invd = vec(vi++);
+    double* bvec = vec(vi++);
+    double* x = vec(vi++);
+    double* r = vec(vi++);
+    double* rh = vec(vi++);
+    double* pv = vec(vi++);
+    double* ph = vec(vi++);
+    double* v = vec(vi++);
+    double* sv = vec(vi++);
+    double* shv = vec(vi++);
+    double* tv = vec(vi++);
+    double* partials = vec(vi);
+    KrylovScalars* ks = reinterpret_cast<KrylovScalars*>(partials + 2 * RED_BLOCKS);
+    const dim3 g((unsigned)((P + BLK - 1) / BLK)), b(BLK);
+    StageArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nslices = op->nslices;
+    a.slices = op->slices;
+    a.lidx = op->lidx;
+    a.halo = op->halo;
+    a.wd64 = op->wd64;
+    ReactParams rp;
+    std::memset(&rp, 0, sizeof(rp));
+    const int np = reaction == RBFFD_REACT_SCHNAKENBERG ? 3 : (reaction == RBFFD_REACT_TURING ? 5 : 0);
+    for (int i = 0; i < np; ++i) rp.p[i] = params[i];
+    // history: state (and the caller's earlier states, if any) into internal order
+    const int have0 = history ? order : 1;
+    for (int s = 0; s < S; ++s) {
+        hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, 1, state + (size_t)s * N, op->perm, U[s][0]);
+        for (int j = 1; j < have0; ++j)
+            hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, 1,
+                               history + ((size_t)(j - 1) * S + s) * N, op->perm, U[s][j]);
+        if (forcing)
+            hipLaunchKernelGGL(k_load_state<double>, g, b, 0, st, P, N, 1, forcing + (size_t)s * N, op->perm, Fi[s]);
+    }
+    auto eval_reaction = [&](int j) {
+        if (!react) return;
+        if (reaction == RBFFD_REACT_SCHNAKENBERG)
+            hipLaunchKernelGGL(k_reaction2<RBFFD_REACT_SCHNAKENBERG>, g, b, 0, st, P, U[0][j], U[1][j], rp, Rh[0][j],
+                               Rh[1][j]);
+        else
+            hipLaunchKernelGGL(k_reaction2<RBFFD_REACT_TURING>, g, b, 0, st, P, U[0][j], U[1][j], rp, Rh[0][j], Rh[1][j]);
+    };
+    for (int j = 0; j < have0; ++j) eval_reaction(j);
+    HIP_TRY(ctx, hipGetLastError());
+    // ring of history slots: slot[j] = index into U/Rh of u^{n-j}
+    int slot[4] = {0, 1, 2, 3};
+    int have = have0;
+    int64_t iters = 0;
+    double worst = 0.0;
+    int result = RBFFD_OK;
+    const unsigned rg = RED_BLOCKS;
+    for (int64_t n = 0; n < nsteps && result == RBFFD_OK; ++n) {
+        const int k = std::min(order, have);
+        const BdfCoef c = bdf_coef(k);
+        const double t1 = t0 + (double)(n + 1) * dt;
+        // the new state goes to the oldest slot (order == k) or the next free one
+        const int newslot = have < order ? slot[have] : slot[order - 1];
+        for (int s = 0; s < S; ++s) {
+            HistPtrs h;
+            std::memset(&h, 0, sizeof(h));
+            for (int j = 0; j < k; ++j) {
+                h.u[j] = U[s][slot[j]];
+                h.r[j] = react ? Rh[s][slot[j]] : nullptr;
+            }
+            const double ef = forcing ? std::exp(lambda * t1) : 0.0;
+            hipLaunchKernelGGL(k_bdf_rhs, g, b, 0, st, P, k, c, h, forcing ? (const double*)Fi[s] : nullptr, ef, dt,
+                               op->perm, bvec);
+            const double gamma = dt * D[s] / c.a[0];
+            hipLaunchKernelGGL(k_inv_diag, g, b, 0, st, P, op->wd64, op->perm, gamma, invd);
+            // start from the current state
+            hipLaunchKernelGGL(k_copy, g, b, 0, st, P, U[s][slot[0]], x);
+            hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, x, gamma, tv);
+            hipLaunchKernelGGL(k_kry_init, g, b, 0, st, P, bvec, tv, r, rh, pv, v);
+            hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, bvec, bvec, r, r, partials);
+            hipLaunchKernelGGL(k_krylov_scalar<0>, dim3(1), dim3(64), 0, st, partials, ks);
+            HIP_TRY(ctx, hipGetLastError());
+            bool conv = false;
+            double relres = 0.0;
+            for (int it = 0; it <= maxit; ++it) {
+                KrylovScalars hs;
+                HIP_TRY(ctx, hipMemcpyAsync(&hs, ks, sizeof(hs), hipMemcpyDeviceToHost, st));
+                HIP_TRY(ctx, hipStreamSynchronize(st));
+                relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : std::sqrt(hs.rr);
+                if (!std::isfinite(relres)) {
+                    result = set_error(ctx, RBFFD_E_NONFINITE, "implicit solve: non-finite residual at step %lld",
+                                       (long long)n);
+                    break;
+                }
+                if (relres <= tol || hs.rr == 0.0) {
+                    conv = true;
+                    break;
+                }
+                if (it == maxit || hs.breakdown) break;
+                ++iters;
+                hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, r, nullptr, nullptr, partials);
+                hipLaunchKernelGGL(k_krylov_scalar<1>, dim3(1), dim3(64), 0, st, partials, ks);
+                hipLaunchKernelGGL(k_kry_p, g, b, 0, st, P, ks, r, pv, v, invd, ph);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, ph, gamma, v);
+                hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, v, nullptr, nullptr, partials);
+                hipLaunchKernelGGL(k_krylov_scalar<2>, dim3(1), dim3(64), 0, st, partials, ks);
+                hipLaunchKernelGGL(k_kry_s, g, b, 0, st, P, ks, r, v, invd, sv, shv);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, shv, gamma, tv);
+                hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, tv, sv, tv, tv, partials);
+                hipLaunchKernelGGL(k_krylov_scalar<3>, dim3(1), dim3(64), 0, st, partials, ks);
+                hipLaunchKernelGGL(k_kry_xr, g, b, 0, st, P, ks, ph, shv, sv, tv, x, r);
+                hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, r, r, nullptr, nullptr, partials);
+                hipLaunchKernelGGL(k_krylov_scalar<4>, dim3(1), dim3(64), 0, st, partials, ks);
+                HIP_TRY(ctx, hipGetLastError());
+            }
+            if (result != RBFFD_OK) break;
+            worst = std::max(worst, relres);
+            hipLaunchKernelGGL(k_copy, g, b, 0, st, P, x, U[s][newslot]);
+            if (!conv) {
+                result = set_error(ctx, RBFFD_E_NOCONV,
+                                   "implicit solve did not reach tol %g in %d iterations (relative residual %g) at "
+                                   "step %lld", tol, maxit, relres, (long long)n);
+            }
+        }
+        if (result != RBFFD_OK) break;
+        // rotate the history: the new state is u^n from here on, then the
+        // previous ones (at most order - 1 of them), then the unused slots
+        int ns[4] = {0, 0, 0, 0};
+        int q = 0;
+        ns[q++] = newslot;
+        for (int j = 0; j < std::min(have, order - 1); ++j) ns[q++] = slot[j];
+        for (int idx = 0; idx < order && q < order; ++idx) {
+            bool used = false;
+            for (int j = 0; j < q; ++j) used = used || ns[j] == idx;
+            if (!used) ns[q++] = idx;
+        }
+        for (int j = 0; j < order; ++j) slot[j] = ns[j];
+        have = std::min(order, have + 1);
+        eval_reaction(slot[0]);
+    }
+    for (int s = 0; s < S; ++s)
+        hipLaunchKernelGGL(k_store_state<double>, g, b, 0, st, P, N, 1, U[s][slot[0]], op->perm, state + (size_t)s * N);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(st));
+    if (iters_out) *iters_out = iters;
+    if (relres_out) *relres_out = worst;
+    return result;
 }
