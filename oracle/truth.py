@@ -12,7 +12,7 @@ from __future__ import annotations
 import mpmath as mp
 import numpy as np
 
-__all__ = ["stencil_weights_mp"]
+__all__ = ["stencil_weights_mp", "stencil_kappa_mp", "bisect_eps_mp"]
 
 
 def _phi_psi(kernel, e2, r2):
@@ -107,3 +107,62 @@ def stencil_weights_mp(Xs, Ns, eps, kernel="mq", degree=2, rank_tol=1e-10, dps=6
             G = Bd[a] * AinvE
             LP += G * G
         return np.array([float(LP[0, j]) for j in range(n)])
+
+
+def _local_matrix_mp(X, e2, kernel, U):
+    n = len(X)
+    r = U.cols
+    A = mp.zeros(n + r, n + r)
+    for i in range(n):
+        for j in range(n):
+            d = [X[i][c] - X[j][c] for c in range(3)]
+            A[i, j] = _phi_psi(kernel, e2, d[0] ** 2 + d[1] ** 2 + d[2] ** 2)[0]
+        for k in range(r):
+            A[i, n + k] = U[i, k]
+            A[n + k, i] = U[i, k]
+    return A
+
+
+def stencil_kappa_mp(Xs, eps, kernel="mq", degree=0, rank_tol=1e-10, dps=50):
+    """kappa_2 of the bordered local matrix (Sec. 5, eq. target_cond:
+    max|lambda| / min|lambda|, A~ symmetric) from its eigenvalues in
+    `dps`-digit arithmetic, for targets beyond what FP64 resolves."""
+    with mp.workdps(dps):
+        X = [[mp.mpf(float(v)) for v in row] for row in Xs]
+        U, _ = _border_mp(X, degree, rank_tol)
+        A = _local_matrix_mp(X, mp.mpf(float(eps)) ** 2, kernel, U)
+        ev = mp.eigsy(A, eigvals_only=True)
+        lam = [abs(ev[i]) for i in range(len(ev))]
+        return float(max(lam) / min(lam))
+
+
+def bisect_eps_mp(Xs, kappa_T, kernel="mq", degree=0, tol=1e-4, lo_mult=0.05, hi_mult=20.0, max_expand=8, dps=50):
+    """The bisection of Sec. 5 (as oracle.shape.bisect_eps: bracket
+    [lo_mult, hi_mult] / rho expanded by halving / doubling, then halving the
+    bracket until it is tol wide; kappa > kappa_T moves lo) with every kappa_2
+    from stencil_kappa_mp.  Returns (eps, status): 0 ok, 2 no bracket."""
+    d = np.asarray(Xs) - np.asarray(Xs)[0]
+    rho = float(np.sqrt(np.max(np.sum(d * d, axis=1))))
+
+    def above(e):
+        return stencil_kappa_mp(Xs, e, kernel, degree, dps=dps) > kappa_T
+
+    lo, hi = lo_mult / rho, hi_mult / rho
+    ok = True
+    t = 0
+    while not above(lo) and t < max_expand:
+        lo *= 0.5
+        t += 1
+    ok = ok and above(lo)
+    t = 0
+    while above(hi) and t < max_expand:
+        hi *= 2.0
+        t += 1
+    ok = ok and not above(hi)
+    while hi - lo > tol:
+        mid = 0.5 * (lo + hi)
+        if above(mid):
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi), (0 if ok else 2)

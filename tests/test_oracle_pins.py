@@ -415,3 +415,27 @@ def test_ic_generators_are_seeded():
     a = schnakenberg_ic(100)
     b = schnakenberg_ic(100)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_kappa_mp_matches_fp64_where_fp64_resolves_it():
+    """The high-precision kappa_2 agrees with the FP64 eigvalsh one to about
+    kappa u where FP64 resolves it, and one node with the ones border gives
+    [[phi(0), 1], [1, 0]] = [[1, 1], [1, 0]] (IMQ), whose eigenvalues
+    (1 +- sqrt 5) / 2 give kappa = (1 + sqrt 5) / (sqrt 5 - 1).  At a target
+    FP64 cannot resolve (kappa ~ 1e18), 50 and 80 digits agree."""
+    from oracle.truth import stencil_kappa_mp
+
+    X, _ = fibonacci_sphere(400)
+    idx = knn(X, 17)
+    for i in (0, 123, 399):
+        for eps in (3.0, 6.0):
+            k64 = stencil_kappa(X[idx[i]], eps, kernel="imq", degree=0)
+            kmp = stencil_kappa_mp(X[idx[i]], eps, kernel="imq", degree=0)
+            assert abs(kmp / k64 - 1.0) < 50 * k64 * U64 + 1e-13, (i, eps, k64, kmp)
+    # one node and the ones border: [[phi(0), 1], [1, 0]] = [[1, 1], [1, 0]]
+    k1 = stencil_kappa_mp(np.zeros((1, 3)), 2.0, kernel="imq", degree=0)
+    assert abs(k1 - (1 + math.sqrt(5)) / (math.sqrt(5) - 1)) < 1e-14
+    s = idx[7]
+    k50 = stencil_kappa_mp(X[s], 0.05, kernel="imq", degree=0, dps=50)
+    k80 = stencil_kappa_mp(X[s], 0.05, kernel="imq", degree=0, dps=80)
+    assert k50 > 1e15 and abs(k50 / k80 - 1.0) < 1e-12
