@@ -138,6 +138,25 @@ int rbffd_build_weights(rbffd_ctx ctx, int64_t N, const double* xyz, const doubl
                         int32_t* nevals);
 
 /*
+ * Weights in extended precision (Sec. 6.2 computes weights for targets up to
+ * kappa_T = 1e20 in quadruple precision): the same quantities as
+ * rbffd_build_weights for the paper's own local system -- the constant border
+ * (poly_degree 0) with the MQ or IMQ kernel -- with every quantity derived
+ * from the FP64 inputs held as a double-double (about 32 digits): kernel
+ * values, unit normals, the tridiagonal form and Sturm counts behind kappa_2
+ * (so the bisection of Sec. 5 works for kappa_T well beyond 1e16), and a
+ * pivoted LU for the solves.  eps, kappa and w are rounded to FP64.  Same
+ * arguments as rbffd_build_weights; n + 1 <= 48; eps modes FIXED, GIVEN and
+ * BISECT.  One wavefront per stencil, much slower than the FP64 path.
+ * Errors: as rbffd_build_weights; RBFFD_E_UNSUPPORTED for another kernel,
+ * degree, mode or n + 1 > 48.
+ */
+int rbffd_build_weights_dd(rbffd_ctx ctx, int64_t N, const double* xyz, const double* nrm,
+                           const rbffd_weight_opts* opts, const int32_t* idx_in, const double* eps_in,
+                           int32_t* idx_out, double* w, double* eps, double* kappa, int32_t* status,
+                           int32_t* nevals);
+
+/*
  * kappa_2 of every stencil's bordered local matrix at the given eps (Sec. 5,
  * eq. target_cond): max|lambda| / min|lambda|.  Inputs as rbffd_build_weights;
  * eps_in is required.  kappa: N FP64 output.

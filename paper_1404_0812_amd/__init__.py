@@ -159,7 +159,12 @@ class Weights:
     nevals: torch.Tensor
 
 
-def build_weights(xyz, nrm, n, idx=None, eps_in=None, ctx=None, **kw):
+def build_weights_dd(xyz, nrm, n, idx=None, eps_in=None, ctx=None, **kw):
+    """build_weights in double-double arithmetic (constant border, MQ/IMQ, n + 1 <= 48)."""
+    return build_weights(xyz, nrm, n, idx=idx, eps_in=eps_in, ctx=ctx, _entry="rbffd_build_weights_dd", **kw)
+
+
+def build_weights(xyz, nrm, n, idx=None, eps_in=None, ctx=None, _entry="rbffd_build_weights", **kw):
     """RBF-FD weights of the projected surface Laplacian (see make_opts for keywords)."""
     ctx = ctx or default_context()
     o = make_opts(n, **kw)
@@ -176,9 +181,9 @@ def build_weights(xyz, nrm, n, idx=None, eps_in=None, ctx=None, **kw):
     st = torch.empty(N, dtype=torch.int32, device=dev)
     ne = torch.empty(N, dtype=torch.int32, device=dev)
     ctx.enter(xyz, nrm, idx_in, eps_t, idx_out, w, eps, kap, st, ne)
-    ctx.check(ctx.lib.rbffd_build_weights(ctx.h, N, _ptr(xyz), _ptr(nrm), ctypes.byref(o), _ptr(idx_in),
-                                          _ptr(eps_t), _ptr(idx_out) if idx_in is None else ctypes.c_void_p(0),
-                                          _ptr(w), _ptr(eps), _ptr(kap), _ptr(st), _ptr(ne)))
+    ctx.check(getattr(ctx.lib, _entry)(ctx.h, N, _ptr(xyz), _ptr(nrm), ctypes.byref(o), _ptr(idx_in),
+                                       _ptr(eps_t), _ptr(idx_out) if idx_in is None else ctypes.c_void_p(0),
+                                       _ptr(w), _ptr(eps), _ptr(kap), _ptr(st), _ptr(ne)))
     ctx.leave()
     return Weights(idx_out, w, eps, kap, st, ne)
 

@@ -97,6 +97,9 @@ SIGNATURES = {
     "rbffd_build_weights": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, ctypes.POINTER(WeightOpts),
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                       c_void_p]),
+    "rbffd_build_weights_dd": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, ctypes.POINTER(WeightOpts),
+                                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                         c_void_p]),
     "rbffd_kappa": (c_int32, [c_void_p, c_int64, c_void_p, ctypes.POINTER(WeightOpts), c_void_p, c_void_p,
                               c_void_p]),
     "rbffd_op_create": (c_int32, [c_void_p, c_int64, c_int32, c_void_p, c_void_p, c_void_p,

@@ -22,7 +22,7 @@ ARCH = os.environ.get("RBFFD_ARCH", "gfx950")
 # Longest first.
 SOURCES = [("weights_kernels.hip", f"weights_k{k}_nb{nb}", [f"-DRBW_K={k}", f"-DRBW_NB={nb}"])
            for nb in (2, 1) for k in (0, 1, 2)]
-SOURCES += [("mlp.hip", "mlp", []), ("step.hip", "step", []), ("grid_knn.hip", "grid_knn", []),
+SOURCES += [("weights_dd.hip", "weights_dd", []), ("mlp.hip", "mlp", []), ("step.hip", "step", []), ("grid_knn.hip", "grid_knn", []),
             ("context.cpp", "context", []), ("batched.cpp", "batched", []), ("weights.cpp", "weights", [])]
 
 # Packed FP32 instructions are disabled for all device code: the compiler
