@@ -10,8 +10,10 @@ Problems (the paper's, eqs. sph_forced, torus, torus_forced):
 Stencils n = 11, 17, 31 with the paper's radial kernel (inverse multiquadric)
 and constant border; eps per stencil by bisection to kappa_T.  kappa_T
 schedule (Sec. 6.1: from 1e5 at the smallest N growing to 1e18 at the
-largest): log-linear in N between those ends, capped at 1e14, the largest
-target FP64 weights reach (the paper switched to quad precision above it).
+largest): log-linear in N between those ends, either capped at 1e14 with
+FP64 weights, or uncapped with double-double weights above 1e13 (the paper
+switched to quad precision there); and the fixed targets of Sec. 6.2, 1e14
+(FP64) and 1e20 (double-double).
 Time stepping: RK4 with dt = min(1e-4, 0.5 * 2.785 / rho(L)), small enough
 that the spatial error dominates; and, for the forced sphere, the paper's own
 BDF4 at dt = 1e-4 started from the exact solution.  Errors: relative l2
@@ -54,6 +56,18 @@ def kappa_schedule(N, Nmin, Nmax, cap=1e14):
     return min(cap, 10.0 ** (5.0 + 13.0 * f))
 
 
+def target(schedule, N, Ns):
+    """(kappa_T, double-double weights?) for a schedule."""
+    if schedule == "growing":
+        return kappa_schedule(N, Ns[0], Ns[-1]), False
+    if schedule == "growing_dd":  # the paper's schedule uncapped, weights in double-double above 1e13
+        k = kappa_schedule(N, Ns[0], Ns[-1], cap=1e18)
+        return k, k > 1e13
+    if schedule == "fixed1e14":
+        return 1e14, False
+    return 1e20, True  # fixed1e20: Sec. 6.2's second target, all weights in double-double
+
+
 def problem(name, size):
     """(X, nrm, u0, exact(t), forcing F or None, final t)."""
     if name in ("heat", "fsphere"):
@@ -82,9 +96,10 @@ def spectral_radius(op, N, iters=80):
     return lam
 
 
-def run(lib, X, nrm, u0, F, tf, n, kT, stepper="rk4", exact=None):
+def run(lib, X, nrm, u0, F, tf, n, kT, stepper="rk4", exact=None, dd=False):
     Xd, Nd = dev(X), dev(nrm)
-    res = lib.build_weights(Xd, Nd, n, eps_mode="bisect", kappa_target=kT, **KW)
+    build = lib.build_weights_dd if dd else lib.build_weights
+    res = build(Xd, Nd, n, eps_mode="bisect", kappa_target=kT, **KW)
     _, perm = lib.knn(Xd, n)
     op = lib.Operator(res.idx, res.w, perm=perm)
     kw = dict(forcing=dev(F[None, :]), t0=0.0, lam=-5.0) if F is not None else {}
@@ -149,7 +164,9 @@ FLOOR = {11: 1.5, 17: 2.5, 31: 3.0}
 # two forced problems with the target fixed at 1e14 (and 1e20 in quad precision).
 @pytest.mark.parametrize("name,schedule,stepper", [("heat", "growing", "rk4"), ("fsphere", "growing", "rk4"),
                                                    ("ftorus", "growing", "rk4"), ("fsphere", "fixed1e14", "rk4"),
-                                                   ("ftorus", "fixed1e14", "rk4"), ("fsphere", "growing", "bdf4")])
+                                                   ("ftorus", "fixed1e14", "rk4"), ("fsphere", "growing", "bdf4"),
+                                                   ("fsphere", "growing_dd", "rk4"), ("ftorus", "growing_dd", "rk4"),
+                                                   ("fsphere", "fixed1e20", "rk4"), ("ftorus", "fixed1e20", "rk4")])
 def test_convergence_orders(lib, name, schedule, stepper):
     sizes = SIZES[name]
     probs = [problem(name, s) for s in sizes]
@@ -157,8 +174,8 @@ def test_convergence_orders(lib, name, schedule, stepper):
     for n in (11, 17, 31):
         rows = []
         for (X, nrm, u0, exact, F, tf), N in zip(probs, Ns):
-            kT = kappa_schedule(N, Ns[0], Ns[-1]) if schedule == "growing" else 1e14
-            u, res, dt, steps = run(lib, X, nrm, u0, F, tf, n, kT, stepper, exact)
+            kT, dd = target(schedule, N, Ns)
+            u, res, dt, steps = run(lib, X, nrm, u0, F, tf, n, kT, stepper, exact, dd)
             ue = exact(tf)
             assert np.all(np.isfinite(u)), (name, N, n)
             e2 = np.linalg.norm(u - ue) / np.linalg.norm(ue)
