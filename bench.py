@@ -323,6 +323,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the implicit-stepping and double-double sections")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -556,6 +557,56 @@ def run_bench(args, torch, X, nrm, pool):
     if not args.no_batched:
         batched = batched_section(rb, ctx)
 
+    implicit = None
+    if not args.no_extra:
+        # semi-implicit BDF2 on the same operator and kinetics, FP64, at 50x the
+        # RK4 step: time per step and Krylov iterations (untimed in the headline)
+        op_i = rb.Operator(idx, res.w, perm=perm, ctx=ctx)
+        dt_i = 50.0 * dt_rk4
+        op_i.step_imex(state0, dt_i, 2, order=2, D=DIFF, reaction="schnakenberg", params=SCHNAK)  # warm
+        torch.cuda.synchronize()
+        t0i = time.perf_counter()
+        steps_i = 20
+        out_i, its_i, res_i = op_i.step_imex(state0, dt_i, steps_i, order=2, D=DIFF, reaction="schnakenberg",
+                                             params=SCHNAK)
+        torch.cuda.synchronize()
+        ms_i = (time.perf_counter() - t0i) * 1e3 / steps_i
+        implicit = {"scheme": "SBDF2 (implicit diffusion, explicit kinetics), BiCGSTAB + Jacobi, tol 1e-12, FP64",
+                    "dt": dt_i, "dt_over_rk4_dt": 50.0, "steps": steps_i, "ms_per_step": ms_i,
+                    "krylov_iterations_per_step_and_species": its_i / (2.0 * steps_i), "worst_relres": res_i,
+                    "simulated_time_per_s": dt_i / (ms_i / 1e3),
+                    "rk4_f32_simulated_time_per_s": dt_rk4 / (ms_rk4 / 1e3),
+                    "rk4_f64_simulated_time_per_s": dt_rk4 / (ms_rk4_f64 / 1e3),
+                    "state_finite": bool(torch.isfinite(out_i).all().item())}
+        print(f"[bench] SBDF2 at 50x dt: {ms_i:.2f} ms/step, {implicit['krylov_iterations_per_step_and_species']:.1f} "
+              f"iterations per step and species", flush=True)
+        del op_i
+
+    dd_section = None
+    if not args.no_extra:
+        # double-double weights for a target beyond FP64: the largest icosahedral
+        # node set of the convergence studies, n = 31, kappa_T = 1e18
+        from synth import icosahedral_sphere
+
+        Xi, Ni = icosahedral_sphere(6)
+        Xid, Nid = torch.as_tensor(Xi).cuda(), torch.as_tensor(Ni).cuda()
+        idx_i, _ = rb.knn(Xid, 31, ctx=ctx)
+        torch.cuda.synchronize()
+        a = ev()
+        rdd = rb.build_weights_dd(Xid, Nid, 31, idx=idx_i, ctx=ctx, eps_mode="bisect", kappa_target=1e18,
+                                  kernel="imq", degree=0)
+        b = ev()
+        torch.cuda.synchronize()
+        ms_dd = a.elapsed_time(b)
+        kdd = rdd.kappa.cpu().numpy()
+        dd_section = {"workload": "icosahedral sphere N=40962, n=31, IMQ + constant, bisection to kappa_T=1e18",
+                      "ms": ms_dd, "stencil_weights_per_s": len(Xi) / (ms_dd / 1e3),
+                      "mean_kappa_evals": float(rdd.nevals.float().mean().item()),
+                      "median_log10_kappa": float(np.median(np.log10(kdd))),
+                      "status_counts": {str(k): int(v) for k, v in
+                                        zip(*np.unique(rdd.status.cpu().numpy(), return_counts=True))}}
+        print(f"[bench] double-double weights to 1e18: {ms_dd:.1f} ms", flush=True)
+
     line = {
         "metric": "stencil weights/s + ms per RK4 step at N=1e6,n=50; learned-eps vs bisection",
         "value": value,
@@ -593,6 +644,8 @@ def run_bench(args, torch, X, nrm, pool):
             (compare.get("speedup_learned_vs_band_stop") if compare else None)),
         "learned_vs_bisection": compare,
         "batched": batched,
+        "implicit_sbdf2": implicit,
+        "double_double_weights": dd_section,
     }
     if pool is not None:
         idx_h = idx.cpu().numpy()

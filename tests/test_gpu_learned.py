@@ -120,7 +120,11 @@ def test_trained_network_beats_constant_heuristic(lib):
     fb_l = float((res_l.status == 1).float().mean().item())
     fb_c = float((res_c.status == 1).float().mean().item())
     print(f"mean |log10 kappa/kT|: learned {dev_l:.3f} constant {dev_c:.3f}; fallback {fb_l:.4f} vs {fb_c:.4f}")
-    assert dev_l < dev_c
+    # bars from the recorded measurement (mean deviation 0.318 vs 0.342, ratio
+    # 0.93; fallback 1.5% vs 2.7%) with a margin for the run-to-run spread:
+    # the tangent-plane inputs leave the curvature of the stencil out, which
+    # caps what a network of them can add over one constant eps * rho
+    assert dev_l <= 0.97 * dev_c
     assert fb_l < 0.75 * fb_c
     k = res_l.kappa.cpu().numpy()
     assert np.all((k > 0.99 * band[0]) & (k < 1.01 * band[1]))
