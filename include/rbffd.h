@@ -340,8 +340,11 @@ int rbffd_step_forced(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, double* stat
  * order k; the diffusion and the forcing f_s(t, x_i) = exp(lambda t)
  * forcing[s * N + i] (nullable) are implicit, the reaction explicit.  Each
  * step solves (I - gamma L_X) u_s = rhs_s, gamma = dt D_s / a_0, per species
- * with BiCGSTAB (Jacobi preconditioner, initial guess u^n) to the relative
- * residual tol (the paper: 1e-12), at most maxit iterations.
+ * with unpreconditioned BiCGSTAB (initial guess u^n, restarted from the
+ * true residual after a breakdown) to the relative residual tol (the
+ * paper: 1e-12), at most maxit iterations in all.  No diagonal scaling: on
+ * irregular node sets L_X can have positive diagonal entries, and the
+ * diagonal of I - gamma L_X then crosses zero as dt grows.
  * state: nspecies x N FP64 at time t0, caller order, overwritten with the
  * state after nsteps steps.  history (nullable): the states at t0 - dt,
  * t0 - 2 dt, ..., (order - 1) x nspecies x N (the paper starts BDF4 from the

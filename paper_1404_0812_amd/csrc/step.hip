@@ -1090,10 +1090,15 @@ extern "C" int rbffd_step_forced(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, d
 // diffusion problems and SBDF2 of Sec. 7 for the Turing system): each step
 //   sum_{j=0}^{k} a_j u^{n+1-j} = dt (D L u^{n+1} + f(t_{n+1}) + sum_{j=1}^{k} b_j R(u^{n+1-j})),
 // i.e. (I - gamma L) u_s^{n+1} = rhs_s / a_0 with gamma = dt D_s / a_0, solved
-// per species by BiCGSTAB with a Jacobi (diagonal) preconditioner.  Vectors
-// are FP64 in internal order, one array per species; every scalar of the
-// iteration stays on the device, the host reads the residual norm once per
-// iteration to stop.
+// per species by unpreconditioned BiCGSTAB, restarted from the true residual
+// after a breakdown.  There is no diagonal (Jacobi) scaling on purpose: on
+// irregular node sets some stencils give L a positive diagonal entry, so the
+// diagonal of I - gamma L passes through zero as dt grows and dividing by it
+// wrecks the iteration, while the unscaled system stays well conditioned
+// (its eigenvalues have real part >= 1 whenever L's are in the left half
+// plane, the stability property of Sec. 5).  Vectors are FP64 in internal
+// order, one array per species; every scalar of the iteration stays on the
+// device, the host reads the residual norm once per iteration to stop.
 namespace {
 
 constexpr int RED_BLOCKS = 512;
@@ -1126,6 +1131,7 @@ BdfCoef bdf_coef(int k) {
 struct KrylovScalars {
     double rho, rho_old, alpha, omega, beta;
     double bb, rr;        // ||b||^2, ||r||^2
+    double rr0;           // ||rhat||^2 (the residual at the last start)
     int breakdown;
 };
 
@@ -1163,14 +1169,6 @@ __global__ void k_reaction2(int64_t P, const double* __restrict__ u, const doubl
     reaction<double, R>(y, r, rp);
     ru[p] = r[0];
     rv[p] = r[1];
-}
-
-// Inverse of the diagonal of I - gamma L (0 on padding rows, which then stay 0).
-__global__ void k_inv_diag(int64_t P, const double* __restrict__ wd, const int32_t* __restrict__ perm, double gamma,
-                           double* __restrict__ invd) {
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= P) return;
-    invd[p] = perm[p] >= 0 ? 1.0 / (1.0 - gamma * wd[p]) : 0.0;
 }
 
 // out = x - gamma L x (live rows; padding rows keep their zero)
@@ -1235,8 +1233,9 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ partials
 }
 
 // Scalar steps of the iteration (one wave each).
-// MODE 0: bb = d0, rr = d1, rho_old = alpha = omega = 1 (start)
+// MODE 0: bb = d0, rr = rr0 = d1, rho_old = alpha = omega = 1 (start)
 // MODE 1: rho = d0; beta = (rho / rho_old) (alpha / omega); rho_old = rho
+//         (breakdown when |rho| <= 1e-14 ||rhat|| ||r|| or omega = 0)
 // MODE 2: alpha = rho / d0
 // MODE 3: omega = d0 / d1 (t.s / t.t)
 // MODE 4: rr = d0
@@ -1248,11 +1247,13 @@ __global__ void k_krylov_scalar(const double* __restrict__ partials, KrylovScala
     if (MODE == 0) {
         ks->bb = d0;
         ks->rr = d1;
+        ks->rr0 = d1;
         ks->rho_old = ks->alpha = ks->omega = 1.0;
         ks->breakdown = 0;
     } else if (MODE == 1) {
         const double rho = d0;
-        if (rho == 0.0 || ks->omega == 0.0) ks->breakdown = 1;
+        // rhat (nearly) orthogonal to r, or a zero stabilising step: restart
+        if (!(std::fabs(rho) > 1e-14 * std::sqrt(ks->rr0 * ks->rr)) || ks->omega == 0.0) ks->breakdown = 1;
         ks->beta = ks->breakdown ? 0.0 : (rho / ks->rho_old) * (ks->alpha / ks->omega);
         ks->rho = rho;
         ks->rho_old = rho;
@@ -1279,38 +1280,33 @@ __global__ void k_kry_init(int64_t P, const double* __restrict__ b, const double
     v[p] = 0.0;
 }
 
-// p = r + beta (p - omega v); ph = M^-1 p
+// p = r + beta (p - omega v)
 __global__ void k_kry_p(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ r,
-                        double* __restrict__ pv, const double* __restrict__ v, const double* __restrict__ invd,
-                        double* __restrict__ ph) {
+                        double* __restrict__ pv, const double* __restrict__ v) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
     const double beta = ks->beta, omega = ks->omega;
-    const double np = fma(beta, fma(-omega, v[p], pv[p]), r[p]);
-    pv[p] = np;
-    ph[p] = invd[p] * np;
+    pv[p] = fma(beta, fma(-omega, v[p], pv[p]), r[p]);
 }
 
-// s = r - alpha v; sh = M^-1 s
+// s = r - alpha v
 __global__ void k_kry_s(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ r,
-                        const double* __restrict__ v, const double* __restrict__ invd, double* __restrict__ s,
-                        double* __restrict__ sh) {
+                        const double* __restrict__ v, double* __restrict__ s) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const double sv = fma(-ks->alpha, v[p], r[p]);
-    s[p] = sv;
-    sh[p] = invd[p] * sv;
+    s[p] = fma(-ks->alpha, v[p], r[p]);
 }
 
-// x += alpha ph + omega sh; r = s - omega t
-__global__ void k_kry_xr(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ ph,
-                         const double* __restrict__ sh, const double* __restrict__ s, const double* __restrict__ t,
-                         double* __restrict__ x, double* __restrict__ r) {
+// x += alpha p + omega s; r = s - omega t
+__global__ void k_kry_xr(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ pv,
+                         const double* __restrict__ s, const double* __restrict__ t, double* __restrict__ x,
+                         double* __restrict__ r) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= P) return;
     const double alpha = ks->alpha, omega = ks->omega;
-    x[p] = fma(omega, sh[p], fma(alpha, ph[p], x[p]));
-    r[p] = fma(-omega, t[p], s[p]);
+    const double sv = s[p];
+    x[p] = fma(omega, sv, fma(alpha, pv[p], x[p]));
+    r[p] = fma(-omega, t[p], sv);
 }
 
 __global__ void k_copy(int64_t P, const double* __restrict__ src, double* __restrict__ dst) {
@@ -1357,8 +1353,8 @@ extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, dou
     const int64_t N = op->N, P = op->P;
     const int S = nspecies;
     const bool react = reaction != RBFFD_REACT_NONE;
-    // layout: U[s][order], R[s][order] (reaction), F[s], invd, b, x, r, rh, p, ph, v, s, sh, t; partials; scalars
-    const int nvec = S * order * (react ? 2 : 1) + S + 11;
+    // layout: U[s][order], R[s][order] (reaction), F[s], b, x, r, rh, p, v, s, t; partials; scalars
+    const int nvec = S * order * (react ? 2 : 1) + S + 8;
     const size_t vbytes = (size_t)P * sizeof(double);
     const size_t bytes = nvec * vbytes + 2 * RED_BLOCKS * sizeof(double) + 256;
     int rc = ensure_impl(op, bytes);
@@ -1376,16 +1372,13 @@ extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, dou
             for (int j = 0; j < order; ++j) Rh[s][j] = vec(vi++);
     double* Fi[2] = {};
     for (int s = 0; s < S; ++s) Fi[s] = vec(vi++);
-    double* invd = vec(vi++);
     double* bvec = vec(vi++);
     double* x = vec(vi++);
     double* r = vec(vi++);
     double* rh = vec(vi++);
     double* pv = vec(vi++);
-    double* ph = vec(vi++);
     double* v = vec(vi++);
     double* sv = vec(vi++);
-    double* shv = vec(vi++);
     double* tv = vec(vi++);
     double* partials = vec(vi);
     KrylovScalars* ks = reinterpret_cast<KrylovScalars*>(partials + 2 * RED_BLOCKS);
@@ -1445,13 +1438,16 @@ extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, dou
             hipLaunchKernelGGL(k_bdf_rhs, g, b, 0, st, P, k, c, h, forcing ? (const double*)Fi[s] : nullptr, ef, dt,
                                op->perm, bvec);
             const double gamma = dt * D[s] / c.a[0];
-            hipLaunchKernelGGL(k_inv_diag, g, b, 0, st, P, op->wd64, op->perm, gamma, invd);
-            // start from the current state
+            // (re)start from the true residual of x
+            auto krylov_start = [&]() {
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, x, gamma, tv);
+                hipLaunchKernelGGL(k_kry_init, g, b, 0, st, P, bvec, tv, r, rh, pv, v);
+                hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, bvec, bvec, r, r, partials);
+                hipLaunchKernelGGL(k_krylov_scalar<0>, dim3(1), dim3(64), 0, st, partials, ks);
+            };
+            // initial guess: the current state
             hipLaunchKernelGGL(k_copy, g, b, 0, st, P, U[s][slot[0]], x);
-            hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, x, gamma, tv);
-            hipLaunchKernelGGL(k_kry_init, g, b, 0, st, P, bvec, tv, r, rh, pv, v);
-            hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, bvec, bvec, r, r, partials);
-            hipLaunchKernelGGL(k_krylov_scalar<0>, dim3(1), dim3(64), 0, st, partials, ks);
+            krylov_start();
             HIP_TRY(ctx, hipGetLastError());
             bool conv = false;
             double relres = 0.0;
@@ -1469,19 +1465,24 @@ extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, dou
                     conv = true;
                     break;
                 }
-                if (it == maxit || hs.breakdown) break;
+                if (it == maxit) break;
                 ++iters;
+                if (hs.breakdown) {
+                    krylov_start();
+                    HIP_TRY(ctx, hipGetLastError());
+                    continue;
+                }
                 hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, r, nullptr, nullptr, partials);
                 hipLaunchKernelGGL(k_krylov_scalar<1>, dim3(1), dim3(64), 0, st, partials, ks);
-                hipLaunchKernelGGL(k_kry_p, g, b, 0, st, P, ks, r, pv, v, invd, ph);
-                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, ph, gamma, v);
+                hipLaunchKernelGGL(k_kry_p, g, b, 0, st, P, ks, r, pv, v);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, pv, gamma, v);
                 hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, v, nullptr, nullptr, partials);
                 hipLaunchKernelGGL(k_krylov_scalar<2>, dim3(1), dim3(64), 0, st, partials, ks);
-                hipLaunchKernelGGL(k_kry_s, g, b, 0, st, P, ks, r, v, invd, sv, shv);
-                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, shv, gamma, tv);
+                hipLaunchKernelGGL(k_kry_s, g, b, 0, st, P, ks, r, v, sv);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, sv, gamma, tv);
                 hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, tv, sv, tv, tv, partials);
                 hipLaunchKernelGGL(k_krylov_scalar<3>, dim3(1), dim3(64), 0, st, partials, ks);
-                hipLaunchKernelGGL(k_kry_xr, g, b, 0, st, P, ks, ph, shv, sv, tv, x, r);
+                hipLaunchKernelGGL(k_kry_xr, g, b, 0, st, P, ks, pv, sv, tv, x, r);
                 hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, r, r, nullptr, nullptr, partials);
                 hipLaunchKernelGGL(k_krylov_scalar<4>, dim3(1), dim3(64), 0, st, partials, ks);
                 HIP_TRY(ctx, hipGetLastError());
