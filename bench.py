@@ -30,6 +30,8 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, TFLOP/s
 SCHNAK = (0.1, 0.9, 50.0)   # a, b, gamma
 DIFF = (1.0, 10.0)          # D_u, D_v
 IMEX_MAXIT = 3000          # Krylov iterations per implicit solve in the SBDF2 section
+TURING_DT = 0.01            # Sec. 7's SBDF2 step
+TURING_SPOTS = (0.899, -0.91, -0.899, 0.02, 0.2)  # Table 1: alpha, beta, gamma, tau1, tau2 (spots)
 
 
 def weights_flops(n, r, evals):
@@ -598,7 +600,36 @@ def run_bench(args, torch, X, nrm, pool):
                     "state_finite": bool(torch.isfinite(out_i).all().item())}
         print(f"[bench] SBDF2 at {mult:g}x dt: {ms_i:.2f} ms/step, "
               f"{implicit['krylov_iterations_per_step_and_species']:.1f} iterations per step and species", flush=True)
+    turing = None
     if not args.no_extra:
+        # Sec. 7's own scheme on the point cloud: the Turing spots kinetics of
+        # Table 1 (the point-cloud rows' delta_v, delta_u = 0.516 delta_v),
+        # SBDF2 at dt = 0.01, from U(-0.01, 0.01) noise
+        g = np.random.default_rng(5)
+        s0t = torch.as_tensor(np.stack([g.uniform(-0.01, 0.01, args.N), g.uniform(-0.01, 0.01, args.N)])).cuda()
+        dv = 2.87e-4
+        Dt = (0.516 * dv, dv)
+        try:
+            op_i.step_imex(s0t, TURING_DT, 2, order=2, D=Dt, reaction="turing", params=TURING_SPOTS,
+                           maxit=IMEX_MAXIT)
+            torch.cuda.synchronize()
+            t0t = time.perf_counter()
+            steps_t = 20
+            out_t, its_t, res_t = op_i.step_imex(s0t, TURING_DT, steps_t, order=2, D=Dt, reaction="turing",
+                                                 params=TURING_SPOTS, maxit=IMEX_MAXIT)
+            torch.cuda.synchronize()
+            ms_t = (time.perf_counter() - t0t) * 1e3 / steps_t
+            turing = {"scheme": "SBDF2, unpreconditioned BiCGSTAB, tol 1e-12, FP64",
+                      "kinetics": "Turing spots (alpha 0.899, beta -0.91, gamma -0.899, tau1 0.02, tau2 0.2)",
+                      "delta_v": dv, "dt": TURING_DT, "steps": steps_t, "ms_per_step": ms_t,
+                      "krylov_iterations_per_step_and_species": its_t / (2.0 * steps_t), "worst_relres": res_t,
+                      "simulated_time_per_s": TURING_DT / (ms_t / 1e3),
+                      "state_finite": bool(torch.isfinite(out_t).all().item())}
+            print(f"[bench] Turing SBDF2 at dt = {TURING_DT}: {ms_t:.2f} ms/step, "
+                  f"{turing['krylov_iterations_per_step_and_species']:.1f} iterations per step and species",
+                  flush=True)
+        except rb.RbffdError as err:
+            turing = {"failed": str(err)[:160]}
         del op_i
 
     dd_section = None
@@ -664,6 +695,7 @@ def run_bench(args, torch, X, nrm, pool):
         "learned_vs_bisection": compare,
         "batched": batched,
         "implicit_sbdf2": implicit,
+        "turing_sbdf2_paper_dt": turing,
         "double_double_weights": dd_section,
     }
     if pool is not None:

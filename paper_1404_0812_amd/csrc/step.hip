@@ -1129,11 +1129,19 @@ BdfCoef bdf_coef(int k) {
 
 // Scalars of one BiCGSTAB solve (device).
 struct KrylovScalars {
-    double rho, rho_old, alpha, omega, beta;
+    double rho, alpha, omega, beta;
     double bb, rr;        // ||b||^2, ||r||^2
     double rr0;           // ||rhat||^2 (the residual at the last start)
-    int breakdown;
+    double tol2;          // tol^2
+    int breakdown;        // rhat (nearly) orthogonal to r, or a zero step
+    int done;             // 0 running, 1 converged, 2 restart wanted, 3 non-finite residual
+    int iters;            // iterations done since the solve began (restarts not counted)
+    int pad;
 };
+
+// Iterations launched between two reads of the scalars by the host; the
+// kernels of iterations after convergence (or a breakdown) return at once.
+constexpr int KRYLOV_BATCH = 8;
 
 struct HistPtrs {
     const double* u[4];   // u^n, u^{n-1}, ... (one species)
@@ -1171,10 +1179,13 @@ __global__ void k_reaction2(int64_t P, const double* __restrict__ u, const doubl
     rv[p] = r[1];
 }
 
-// out = x - gamma L x (live rows; padding rows keep their zero)
+// out = x - gamma L x (live rows; padding rows keep their zero); a no-op once
+// the solve is done (ks nullable)
 __global__ __launch_bounds__(BLK) void k_amul(StageArgs a, const int32_t* __restrict__ idx,
                                               const double* __restrict__ w, const double* __restrict__ X,
-                                              double gamma, double* __restrict__ out) {
+                                              double gamma, double* __restrict__ out,
+                                              const KrylovScalars* __restrict__ ks) {
+    if (ks && ks->done) return;
     const RowPos rp = row_pos<double>(a);
     if (rp.slice < 0) return;
     double yi[2] = {0.0, 0.0};
@@ -1205,7 +1216,8 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 template <int NQ>
 __global__ __launch_bounds__(256) void k_dots(int64_t P, const double* __restrict__ a0, const double* __restrict__ b0,
                                               const double* __restrict__ a1, const double* __restrict__ b1,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials, const KrylovScalars* __restrict__ ks) {
+    if (ks && ks->done) return;
     __shared__ double sh[4];
     double s0 = 0.0, s1 = 0.0;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
@@ -1232,38 +1244,60 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ partials
     d1 = wave_sum_block(s1);
 }
 
-// Scalar steps of the iteration (one wave each).
-// MODE 0: bb = d0, rr = rr0 = d1, rho_old = alpha = omega = 1 (start)
-// MODE 1: rho = d0; beta = (rho / rho_old) (alpha / omega); rho_old = rho
-//         (breakdown when |rho| <= 1e-14 ||rhat|| ||r|| or omega = 0)
-// MODE 2: alpha = rho / d0
+// Scalar steps of the iteration (one wave each); every mode but 0 is a no-op
+// once the solve is done.
+// MODE 0 (start; d0 = b.b, d1 = r.r, rhat = r): bb, rr = rr0 = rho = d1,
+//         alpha = omega = 1; iters = 0 on the first start of a solve; done
+//         at once if r already meets tol
+// MODE 2: alpha = rho / d0 (d0 = rhat.v)
 // MODE 3: omega = d0 / d1 (t.s / t.t)
-// MODE 4: rr = d0
+// MODE 4 (end of an iteration; d0 = r.r, d1 = rhat.r): rr = d0; converged,
+//         non-finite, or else rho' = d1 and beta = (rho' / rho) (alpha / omega)
+//         for the next iteration, unless |rho'| <= 1e-14 ||rhat|| ||r|| or
+//         omega = 0 (breakdown: the host restarts from the true residual)
+__device__ __forceinline__ int residual_state(const KrylovScalars* ks, double rr) {
+    if (!(rr <= 1.79e308)) return 3;
+    const double lim = ks->bb > 0.0 ? ks->tol2 * ks->bb : ks->tol2;
+    return rr <= lim ? 1 : 0;
+}
+
 template <int MODE>
-__global__ void k_krylov_scalar(const double* __restrict__ partials, KrylovScalars* __restrict__ ks) {
+__global__ void k_krylov_scalar(const double* __restrict__ partials, KrylovScalars* __restrict__ ks, double tol,
+                                int first) {
+    if (MODE != 0 && ks->done) return;
     double d0, d1;
     sum_partials(partials, d0, d1);
     if (threadIdx.x != 0) return;
     if (MODE == 0) {
         ks->bb = d0;
-        ks->rr = d1;
-        ks->rr0 = d1;
-        ks->rho_old = ks->alpha = ks->omega = 1.0;
+        ks->rr = ks->rr0 = ks->rho = d1;
+        ks->alpha = ks->omega = 1.0;
+        ks->beta = 0.0;
+        ks->tol2 = tol * tol;
         ks->breakdown = 0;
-    } else if (MODE == 1) {
-        const double rho = d0;
-        // rhat (nearly) orthogonal to r, or a zero stabilising step: restart
-        if (!(std::fabs(rho) > 1e-14 * std::sqrt(ks->rr0 * ks->rr)) || ks->omega == 0.0) ks->breakdown = 1;
-        ks->beta = ks->breakdown ? 0.0 : (rho / ks->rho_old) * (ks->alpha / ks->omega);
-        ks->rho = rho;
-        ks->rho_old = rho;
+        if (first) ks->iters = 0;
+        ks->done = residual_state(ks, d1);
     } else if (MODE == 2) {
         if (d0 == 0.0) ks->breakdown = 1;
         ks->alpha = ks->breakdown ? 0.0 : ks->rho / d0;
     } else if (MODE == 3) {
         ks->omega = d1 > 0.0 ? d0 / d1 : 0.0;
     } else {
+        ks->iters += 1;
         ks->rr = d0;
+        const int st = residual_state(ks, d0);
+        if (st) {
+            ks->done = st;
+            return;
+        }
+        const double rho = d1;
+        if (ks->breakdown || !(std::fabs(rho) > 1e-14 * std::sqrt(ks->rr0 * d0)) || ks->omega == 0.0) {
+            ks->breakdown = 1;
+            ks->done = 2;
+            return;
+        }
+        ks->beta = (rho / ks->rho) * (ks->alpha / ks->omega);
+        ks->rho = rho;
     }
 }
 
@@ -1284,7 +1318,7 @@ __global__ void k_kry_init(int64_t P, const double* __restrict__ b, const double
 __global__ void k_kry_p(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ r,
                         double* __restrict__ pv, const double* __restrict__ v) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    if (p >= P || ks->done) return;
     const double beta = ks->beta, omega = ks->omega;
     pv[p] = fma(beta, fma(-omega, v[p], pv[p]), r[p]);
 }
@@ -1293,7 +1327,7 @@ __global__ void k_kry_p(int64_t P, const KrylovScalars* __restrict__ ks, const d
 __global__ void k_kry_s(int64_t P, const KrylovScalars* __restrict__ ks, const double* __restrict__ r,
                         const double* __restrict__ v, double* __restrict__ s) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    if (p >= P || ks->done) return;
     s[p] = fma(-ks->alpha, v[p], r[p]);
 }
 
@@ -1302,7 +1336,7 @@ __global__ void k_kry_xr(int64_t P, const KrylovScalars* __restrict__ ks, const 
                          const double* __restrict__ s, const double* __restrict__ t, double* __restrict__ x,
                          double* __restrict__ r) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= P) return;
+    if (p >= P || ks->done) return;
     const double alpha = ks->alpha, omega = ks->omega;
     const double sv = s[p];
     x[p] = fma(omega, sv, fma(alpha, pv[p], x[p]));
@@ -1439,52 +1473,61 @@ extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, dou
                                op->perm, bvec);
             const double gamma = dt * D[s] / c.a[0];
             // (re)start from the true residual of x
-            auto krylov_start = [&]() {
-                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, x, gamma, tv);
+            auto krylov_start = [&](int first) {
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, x, gamma, tv,
+                                   (const KrylovScalars*)nullptr);
                 hipLaunchKernelGGL(k_kry_init, g, b, 0, st, P, bvec, tv, r, rh, pv, v);
-                hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, bvec, bvec, r, r, partials);
-                hipLaunchKernelGGL(k_krylov_scalar<0>, dim3(1), dim3(64), 0, st, partials, ks);
+                hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, bvec, bvec, r, r, partials,
+                                   (const KrylovScalars*)nullptr);
+                hipLaunchKernelGGL(k_krylov_scalar<0>, dim3(1), dim3(64), 0, st, partials, ks, tol, first);
+            };
+            auto iteration = [&]() {
+                hipLaunchKernelGGL(k_kry_p, g, b, 0, st, P, ks, r, pv, v);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, pv, gamma, v, ks);
+                hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, v, nullptr, nullptr, partials, ks);
+                hipLaunchKernelGGL(k_krylov_scalar<2>, dim3(1), dim3(64), 0, st, partials, ks, tol, 0);
+                hipLaunchKernelGGL(k_kry_s, g, b, 0, st, P, ks, r, v, sv);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, sv, gamma, tv, ks);
+                hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, tv, sv, tv, tv, partials, ks);
+                hipLaunchKernelGGL(k_krylov_scalar<3>, dim3(1), dim3(64), 0, st, partials, ks, tol, 0);
+                hipLaunchKernelGGL(k_kry_xr, g, b, 0, st, P, ks, pv, sv, tv, x, r);
+                hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, r, r, rh, r, partials, ks);
+                hipLaunchKernelGGL(k_krylov_scalar<4>, dim3(1), dim3(64), 0, st, partials, ks, tol, 0);
             };
             // initial guess: the current state
             hipLaunchKernelGGL(k_copy, g, b, 0, st, P, U[s][slot[0]], x);
-            krylov_start();
+            krylov_start(1);
             HIP_TRY(ctx, hipGetLastError());
             bool conv = false;
             double relres = 0.0;
-            for (int it = 0; it <= maxit; ++it) {
+            int restarts = 0;
+            for (;;) {
                 KrylovScalars hs;
                 HIP_TRY(ctx, hipMemcpyAsync(&hs, ks, sizeof(hs), hipMemcpyDeviceToHost, st));
                 HIP_TRY(ctx, hipStreamSynchronize(st));
                 relres = hs.bb > 0.0 ? std::sqrt(hs.rr / hs.bb) : std::sqrt(hs.rr);
-                if (!std::isfinite(relres)) {
+                if (hs.done == 3 || !std::isfinite(relres)) {
                     result = set_error(ctx, RBFFD_E_NONFINITE, "implicit solve: non-finite residual at step %lld",
                                        (long long)n);
                     break;
                 }
-                if (relres <= tol || hs.rr == 0.0) {
+                if (hs.done == 1) {
                     conv = true;
+                    iters += hs.iters + restarts;
                     break;
                 }
-                if (it == maxit) break;
-                ++iters;
-                if (hs.breakdown) {
-                    krylov_start();
-                    HIP_TRY(ctx, hipGetLastError());
-                    continue;
+                const int used = hs.iters + restarts;
+                if (used >= maxit) {
+                    iters += used;
+                    break;
                 }
-                hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, r, nullptr, nullptr, partials);
-                hipLaunchKernelGGL(k_krylov_scalar<1>, dim3(1), dim3(64), 0, st, partials, ks);
-                hipLaunchKernelGGL(k_kry_p, g, b, 0, st, P, ks, r, pv, v);
-                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, pv, gamma, v);
-                hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, v, nullptr, nullptr, partials);
-                hipLaunchKernelGGL(k_krylov_scalar<2>, dim3(1), dim3(64), 0, st, partials, ks);
-                hipLaunchKernelGGL(k_kry_s, g, b, 0, st, P, ks, r, v, sv);
-                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, sv, gamma, tv);
-                hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, tv, sv, tv, tv, partials);
-                hipLaunchKernelGGL(k_krylov_scalar<3>, dim3(1), dim3(64), 0, st, partials, ks);
-                hipLaunchKernelGGL(k_kry_xr, g, b, 0, st, P, ks, pv, sv, tv, x, r);
-                hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, r, r, nullptr, nullptr, partials);
-                hipLaunchKernelGGL(k_krylov_scalar<4>, dim3(1), dim3(64), 0, st, partials, ks);
+                if (hs.done == 2) {
+                    ++restarts;
+                    krylov_start(0);
+                } else {
+                    const int batch = std::min(KRYLOV_BATCH, maxit - used);
+                    for (int q = 0; q < batch; ++q) iteration();
+                }
                 HIP_TRY(ctx, hipGetLastError());
             }
             if (result != RBFFD_OK) break;
