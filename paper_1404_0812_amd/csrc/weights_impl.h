@@ -85,6 +85,16 @@ __device__ __forceinline__ double readlane64(double v, int lane) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
                             __builtin_amdgcn_readlane(__double2loint(v), lane));
 }
+// Four wavefront sums at once: the folds put a, c, b, d in rows 0..3.
+__device__ __forceinline__ void wave_sum4(double& a, double& b, double& c, double& d) {
+    const double s = fold32(a, b);
+    const double t = fold32(c, d);
+    const double u = row_sum16(fold16(s, t));
+    a = readlane64(u, 0);
+    c = readlane64(u, 16);
+    b = readlane64(u, 32);
+    d = readlane64(u, 48);
+}
 // Three wavefront sums at once: a and b share the first fold (a in lanes 0-31,
 // b in 32-63), c is folded with itself, the second fold puts a, c, b, c in
 // rows 0..3, one row sum finishes all three, and lanes 0, 32, 16 hand them
@@ -151,6 +161,7 @@ struct Shared {
     double rhs[3][MM];
     double zb[3][MM];
     double hx[MM], hy[MM], hz[MM];
+    double G[NB == 1 ? 96 : 1];  // Gram entries of the reflectors in blocks of four (one wave)
     double nrm0[3];
     int m, r, n, fact_ok;
 };
@@ -636,11 +647,76 @@ __device__ __forceinline__ void apply_q(const double (&a)[64], Shared<NB>& S, co
     }
 }
 
+// One wave (NB = 1), one vector: Q^T y (FWD) or Q y four reflectors at a time.
+// For a block H_{k0} .. H_{k0+3} the four products d_i = v_i . y are reduced
+// together, and the coupling of successive reflectors inside the block comes
+// from their Gram entries G_ij = v_i . v_j (S.G, six per block, from
+// reflector_gram): applying H_{k0} first, s_i = d_i - sum_{j<i} tau_j s_j G_ij
+// and y -= sum_i tau_i s_i v_i (the reverse order for Q y).  Rows past the last
+// reflector enter with v = 0 and tau = 0.
+template <int NB, bool FWD>
+__device__ __forceinline__ void apply_q_blocked(const double (&a)[64], Shared<NB>& S, double& y) {
+    static_assert(NB == 1, "one-wave tiling only");
+    const int p = S.m - 2;
+#pragma unroll
+    for (int bb = 0; bb < 16; ++bb) {
+        const int b = FWD ? bb : 15 - bb;
+        const int k0 = 4 * b;
+        if (k0 < p) {
+            const double v0 = a[k0], v1 = k0 + 1 < p ? a[k0 + 1] : 0.0;
+            const double v2 = k0 + 2 < p ? a[k0 + 2] : 0.0, v3 = k0 + 3 < p ? a[k0 + 3] : 0.0;
+            const double t0 = S.tau[k0], t1 = k0 + 1 < p ? S.tau[k0 + 1] : 0.0;
+            const double t2 = k0 + 2 < p ? S.tau[k0 + 2] : 0.0, t3 = k0 + 3 < p ? S.tau[k0 + 3] : 0.0;
+            double d0 = v0 * y, d1 = v1 * y, d2 = v2 * y, d3 = v3 * y;
+            wave_sum4(d0, d1, d2, d3);
+            const double* G = S.G + 6 * b;  // G01 G02 G03 G12 G13 G23
+            double s0, s1, s2, s3;
+            if (FWD) {
+                s0 = d0;
+                s1 = fma(-t0 * s0, G[0], d1);
+                s2 = fma(-t1 * s1, G[3], fma(-t0 * s0, G[1], d2));
+                s3 = fma(-t2 * s2, G[5], fma(-t1 * s1, G[4], fma(-t0 * s0, G[2], d3)));
+            } else {
+                s3 = d3;
+                s2 = fma(-t3 * s3, G[5], d2);
+                s1 = fma(-t2 * s2, G[3], fma(-t3 * s3, G[4], d1));
+                s0 = fma(-t1 * s1, G[0], fma(-t2 * s2, G[1], fma(-t3 * s3, G[2], d0)));
+            }
+            y = fma(-t3 * s3, v3, fma(-t2 * s2, v2, fma(-t1 * s1, v1, fma(-t0 * s0, v0, y))));
+        }
+    }
+}
+
+// S.G for apply_q_blocked (one wave, after the final tridiagonalisation).
+template <int NB>
+__device__ __forceinline__ void reflector_gram(const double (&a)[64], Shared<NB>& S, const Tid& t) {
+    static_assert(NB == 1, "one-wave tiling only");
+    const int p = S.m - 2;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const int k0 = 4 * b;
+        if (k0 < p) {
+            const double v0 = a[k0], v1 = k0 + 1 < p ? a[k0 + 1] : 0.0;
+            const double v2 = k0 + 2 < p ? a[k0 + 2] : 0.0, v3 = k0 + 3 < p ? a[k0 + 3] : 0.0;
+            double g01 = v0 * v1, g02 = v0 * v2, g03 = v0 * v3, g12 = v1 * v2;
+            double g13 = v1 * v3, g23 = v2 * v3, z0 = 0.0, z1 = 0.0;
+            wave_sum4(g01, g02, g03, g12);
+            wave_sum4(g13, g23, z0, z1);
+            if (t.tid == 0) {
+                double* G = S.G + 6 * b;
+                G[0] = g01; G[1] = g02; G[2] = g03; G[3] = g12; G[4] = g13; G[5] = g23;
+            }
+        }
+    }
+    bsync<NB>();
+}
+
 // y <- A~^{-1} y via Q T^{-1} Q^T
 template <int NB, int NV>
 __device__ __forceinline__ void solve(const double (&a)[64], Shared<NB>& S, const Tid& t, double (&y)[3]) {
     const int m = S.m;
-    apply_q<NB, NV, true>(a, S, t, y);
+    if constexpr (NB == 1 && NV == 1) apply_q_blocked<NB, true>(a, S, y[0]);
+    else apply_q<NB, NV, true>(a, S, t, y);
     if (t.rb == 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.rhs[v][t.c] = y[v];
@@ -651,7 +727,8 @@ __device__ __forceinline__ void solve(const double (&a)[64], Shared<NB>& S, cons
 #pragma unroll
     for (int v = 0; v < NV; ++v) y[v] = t.c < m ? S.rhs[v][t.c] : 0.0;
     bsync<NB>();
-    apply_q<NB, NV, false>(a, S, t, y);
+    if constexpr (NB == 1 && NV == 1) apply_q_blocked<NB, false>(a, S, y[0]);
+    else apply_q<NB, NV, false>(a, S, t, y);
 }
 
 // (A~ z) row t.c for NV vectors read from S.zb; A~ re-evaluated from the nodes
@@ -1016,6 +1093,7 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
         b[1] = gy - n0y * dn;
         b[2] = gz - n0z * dn;
     }
+    if constexpr (NB == 1) reflector_gram<NB>(a, S, t);
     // g_d: plain solve.  Refining this solve as well as the final one does not
     // lower the error of w (measured against 60-digit weights: both ways
     // 0.02-0.07 kappa u at kappa_T = 1e10 and 1e12; without any refinement
