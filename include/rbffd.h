@@ -127,8 +127,8 @@ int rbffd_knn(rbffd_ctx ctx, int64_t N, const double* xyz, int32_t n, int32_t* i
  * for GIVEN/LEARNED modes (NULL otherwise).
  * Outputs: w (N x n FP64), eps (N, nullable), kappa (N, nullable: kappa_2 of
  * the bordered local matrix at the returned eps; for a LEARNED proposal kept
- * inside the band its eigenvalue search stops at 0.05 band_lo u relative, u =
- * 2^-53, below the ~kappa u the reduction itself allows), status (N int32, nullable),
+ * inside the band its eigenvalue search stops at band_lo u relative, u =
+ * 2^-53, the level of the ~kappa u the reduction itself allows), status (N int32, nullable),
  * nevals (N int32, nullable: number of kappa_2 evaluations of the stencil).
  * Errors: as rbffd_knn; kernel/degree/mode out of range; n + border > 128.
  */

@@ -56,7 +56,7 @@ def test_learned_mode_band_check_and_fallback(lib, torus):
 def test_kept_proposals_report_kappa_low_band(lib, torus):
     """Well-conditioned band [1e5, 1e7]: proposals at the bisected eps for
     kappa_T = 1e6 are all kept, and their kappa_2 (eigenvalue search stopped at
-    0.05 band_lo u) matches the oracle's to 20 kappa u."""
+    band_lo u) matches the oracle's to 20 kappa u."""
     X, nrm, idx = torus
     Xd, Nd, I = dev(X), dev(nrm), dev(idx, torch.int32)
     b = lib.build_weights(Xd, Nd, 50, idx=I, eps_mode="bisect", kappa_target=1e6)
