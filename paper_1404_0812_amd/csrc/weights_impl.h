@@ -129,19 +129,37 @@ __device__ __forceinline__ double recip(double q) {
 }
 
 // ---------------------------------------------------------- radial kernels ----
+// sqrt(x) for x >= 1: the hardware reciprocal square root y ~ 1/sqrt(x),
+// then g = x y, h = y / 2 refined by one coupled Newton step and two
+// residual corrections g += (x - g^2) h, the last of which rounds correctly.
+// The general square root adds a rescaling for tiny arguments and a class
+// check (seven more instructions); the radial kernels' argument 1 + eps^2 r^2
+// never needs them (for x >= 1 the two give the same bits; a non-finite x
+// gives a non-finite result either way).
+__device__ __forceinline__ double sqrt_ge1(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
 template <int K>
 __device__ __forceinline__ double rbf_phi(double e2, double r2) {
     double e = e2 * r2;
-    if (K == RBFFD_KERNEL_MQ) return sqrt(1.0 + e);
-    if (K == RBFFD_KERNEL_IMQ) return 1.0 / sqrt(1.0 + e);
+    if (K == RBFFD_KERNEL_MQ) return sqrt_ge1(1.0 + e);
+    if (K == RBFFD_KERNEL_IMQ) return 1.0 / sqrt_ge1(1.0 + e);
     return exp(-e);
 }
 // phi'(r)/r
 template <int K>
 __device__ __forceinline__ double rbf_psi(double e2, double r2) {
     double e = e2 * r2;
-    if (K == RBFFD_KERNEL_MQ) return e2 / sqrt(1.0 + e);
-    if (K == RBFFD_KERNEL_IMQ) return -e2 / (sqrt(1.0 + e) * (1.0 + e));
+    if (K == RBFFD_KERNEL_MQ) return e2 / sqrt_ge1(1.0 + e);
+    if (K == RBFFD_KERNEL_IMQ) return -e2 / (sqrt_ge1(1.0 + e) * (1.0 + e));
     return -2.0 * e2 * exp(-e);
 }
 
