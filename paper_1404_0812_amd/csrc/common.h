@@ -57,6 +57,10 @@ struct rbffd_op_s {
     size_t impl_bytes = 0;
     // captured graph cache
     hipGraphExec_t graph = nullptr;
+    // graph of KRYLOV_BATCH implicit-solver iterations, valid while its
+    // vectors sit where they were when it was captured (kgraph_key)
+    hipGraphExec_t kgraph = nullptr;
+    const void* kgraph_key = nullptr;
     int graph_key_species = -1, graph_key_prec = -1, graph_key_react = -1, graph_key_steps = -1;
     double graph_key_dt = 0.0;
     double graph_key_D[2] = {0, 0};

@@ -660,6 +660,14 @@ void reset_graph(rbffd_op op) {
     op->graph_key_species = -1;
 }
 
+void reset_kgraph(rbffd_op op) {
+    if (op->kgraph) {
+        (void)hipGraphExecDestroy(op->kgraph);
+        op->kgraph = nullptr;
+    }
+    op->kgraph_key = nullptr;
+}
+
 // Build the sliced operator of nsurf surfaces (validated by the callers).
 int create_op(rbffd_ctx ctx, int nsurf, const rbffd_op_surface* surf, rbffd_op* out) {
     std::vector<OpSlice> sl;
@@ -794,6 +802,7 @@ extern "C" int rbffd_op_destroy(rbffd_op op) {
     if (!op) return RBFFD_E_ARG;
     if (op->ctx) (void)hipStreamSynchronize(op->ctx->stream);
     reset_graph(op);
+    reset_kgraph(op);
     if (op->slices) (void)hipFree(op->slices);
     if (op->wd64) (void)hipFree(op->wd64);
     if (op->w64) (void)hipFree(op->w64);
@@ -1133,6 +1142,7 @@ struct KrylovScalars {
     double bb, rr;        // ||b||^2, ||r||^2
     double rr0;           // ||rhat||^2 (the residual at the last start)
     double tol2;          // tol^2
+    double gamma;         // the solve's I - gamma L (read by the operator kernel)
     int breakdown;        // rhat (nearly) orthogonal to r, or a zero step
     int done;             // 0 running, 1 converged, 2 restart wanted, 3 non-finite residual
     int iters;            // iterations done since the solve began (restarts not counted)
@@ -1179,13 +1189,17 @@ __global__ void k_reaction2(int64_t P, const double* __restrict__ u, const doubl
     rv[p] = r[1];
 }
 
-// out = x - gamma L x (live rows; padding rows keep their zero); a no-op once
-// the solve is done (ks nullable)
+// out = x - gamma L x (live rows; padding rows keep their zero).  With ks
+// (inside the iteration, also inside its graph) gamma comes from ks and the
+// kernel is a no-op once the solve is done.
 __global__ __launch_bounds__(BLK) void k_amul(StageArgs a, const int32_t* __restrict__ idx,
                                               const double* __restrict__ w, const double* __restrict__ X,
                                               double gamma, double* __restrict__ out,
                                               const KrylovScalars* __restrict__ ks) {
-    if (ks && ks->done) return;
+    if (ks) {
+        if (ks->done) return;
+        gamma = ks->gamma;
+    }
     const RowPos rp = row_pos<double>(a);
     if (rp.slice < 0) return;
     double yi[2] = {0.0, 0.0};
@@ -1247,8 +1261,8 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ partials
 // Scalar steps of the iteration (one wave each); every mode but 0 is a no-op
 // once the solve is done.
 // MODE 0 (start; d0 = b.b, d1 = r.r, rhat = r): bb, rr = rr0 = rho = d1,
-//         alpha = omega = 1; iters = 0 on the first start of a solve; done
-//         at once if r already meets tol
+//         alpha = omega = 1, tol and gamma stored; iters = 0 on the first
+//         start of a solve; done at once if r already meets tol
 // MODE 2: alpha = rho / d0 (d0 = rhat.v)
 // MODE 3: omega = d0 / d1 (t.s / t.t)
 // MODE 4 (end of an iteration; d0 = r.r, d1 = rhat.r): rr = d0; converged,
@@ -1263,7 +1277,7 @@ __device__ __forceinline__ int residual_state(const KrylovScalars* ks, double rr
 
 template <int MODE>
 __global__ void k_krylov_scalar(const double* __restrict__ partials, KrylovScalars* __restrict__ ks, double tol,
-                                int first) {
+                                int first, double gamma) {
     if (MODE != 0 && ks->done) return;
     double d0, d1;
     sum_partials(partials, d0, d1);
@@ -1274,6 +1288,7 @@ __global__ void k_krylov_scalar(const double* __restrict__ partials, KrylovScala
         ks->alpha = ks->omega = 1.0;
         ks->beta = 0.0;
         ks->tol2 = tol * tol;
+        ks->gamma = gamma;
         ks->breakdown = 0;
         if (first) ks->iters = 0;
         ks->done = residual_state(ks, d1);
@@ -1352,6 +1367,7 @@ int ensure_impl(rbffd_op op, size_t bytes) {
     if (op->impl_bytes >= bytes) return RBFFD_OK;
     if (op->impl) {
         (void)hipStreamSynchronize(op->ctx->stream);
+        reset_kgraph(op);
         (void)hipFree(op->impl);
         op->impl = nullptr;
         op->impl_bytes = 0;
@@ -1479,20 +1495,44 @@ extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, dou
                 hipLaunchKernelGGL(k_kry_init, g, b, 0, st, P, bvec, tv, r, rh, pv, v);
                 hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, bvec, bvec, r, r, partials,
                                    (const KrylovScalars*)nullptr);
-                hipLaunchKernelGGL(k_krylov_scalar<0>, dim3(1), dim3(64), 0, st, partials, ks, tol, first);
+                hipLaunchKernelGGL(k_krylov_scalar<0>, dim3(1), dim3(64), 0, st, partials, ks, tol, first, gamma);
             };
+            // one iteration; every kernel takes its scalars (gamma too) from ks,
+            // so the same launches serve every species, step and tolerance
             auto iteration = [&]() {
                 hipLaunchKernelGGL(k_kry_p, g, b, 0, st, P, ks, r, pv, v);
-                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, pv, gamma, v, ks);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, pv, 0.0, v, ks);
                 hipLaunchKernelGGL(k_dots<1>, dim3(rg), dim3(256), 0, st, P, rh, v, nullptr, nullptr, partials, ks);
-                hipLaunchKernelGGL(k_krylov_scalar<2>, dim3(1), dim3(64), 0, st, partials, ks, tol, 0);
+                hipLaunchKernelGGL(k_krylov_scalar<2>, dim3(1), dim3(64), 0, st, partials, ks, 0.0, 0, 0.0);
                 hipLaunchKernelGGL(k_kry_s, g, b, 0, st, P, ks, r, v, sv);
-                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, sv, gamma, tv, ks);
+                hipLaunchKernelGGL(k_amul, stage_grid(a.nslices), b, 0, st, a, op->idx32, op->w64, sv, 0.0, tv, ks);
                 hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, tv, sv, tv, tv, partials, ks);
-                hipLaunchKernelGGL(k_krylov_scalar<3>, dim3(1), dim3(64), 0, st, partials, ks, tol, 0);
+                hipLaunchKernelGGL(k_krylov_scalar<3>, dim3(1), dim3(64), 0, st, partials, ks, 0.0, 0, 0.0);
                 hipLaunchKernelGGL(k_kry_xr, g, b, 0, st, P, ks, pv, sv, tv, x, r);
                 hipLaunchKernelGGL(k_dots<2>, dim3(rg), dim3(256), 0, st, P, r, r, rh, r, partials, ks);
-                hipLaunchKernelGGL(k_krylov_scalar<4>, dim3(1), dim3(64), 0, st, partials, ks, tol, 0);
+                hipLaunchKernelGGL(k_krylov_scalar<4>, dim3(1), dim3(64), 0, st, partials, ks, 0.0, 0, 0.0);
+            };
+            // KRYLOV_BATCH iterations from one HIP graph (88 launches), captured
+            // once per operator and vector layout
+            auto batch_graph = [&]() -> int {
+                if (!op->kgraph || op->kgraph_key != (const void*)x) {
+                    reset_kgraph(op);
+                    hipGraph_t graph;
+                    HIP_TRY(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    for (int q = 0; q < KRYLOV_BATCH; ++q) iteration();
+                    hipError_t ce = hipStreamEndCapture(st, &graph);
+                    if (ce != hipSuccess)
+                        return set_error(ctx, RBFFD_E_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+                    hipError_t ie = hipGraphInstantiate(&op->kgraph, graph, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(graph);
+                    if (ie != hipSuccess) {
+                        op->kgraph = nullptr;
+                        return set_error(ctx, RBFFD_E_HIP, "graph instantiate failed: %s", hipGetErrorString(ie));
+                    }
+                    op->kgraph_key = x;
+                }
+                HIP_TRY(ctx, hipGraphLaunch(op->kgraph, st));
+                return RBFFD_OK;
             };
             // initial guess: the current state
             hipLaunchKernelGGL(k_copy, g, b, 0, st, P, U[s][slot[0]], x);
@@ -1524,9 +1564,14 @@ extern "C" int rbffd_step_imex(rbffd_ctx ctx, rbffd_op op, int32_t nspecies, dou
                 if (hs.done == 2) {
                     ++restarts;
                     krylov_start(0);
+                } else if (maxit - used >= KRYLOV_BATCH) {
+                    const int rc = batch_graph();
+                    if (rc) {
+                        result = rc;
+                        break;
+                    }
                 } else {
-                    const int batch = std::min(KRYLOV_BATCH, maxit - used);
-                    for (int q = 0; q < batch; ++q) iteration();
+                    for (int q = 0; q < maxit - used; ++q) iteration();
                 }
                 HIP_TRY(ctx, hipGetLastError());
             }
