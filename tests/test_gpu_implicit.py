@@ -42,7 +42,7 @@ def sphere(lib):
     return X, idx, W, op
 
 
-@pytest.mark.parametrize("order,with_history", [(1, False), (2, False), (4, False), (4, True)])
+@pytest.mark.parametrize("order,with_history", [(1, False), (2, False), (3, False), (3, True), (4, False), (4, True)])
 def test_bdf_forced_heat_matches_oracle(lib, sphere, order, with_history):
     """u_t = L u + exp(-5 t) F on the unit sphere with u = exp(-5t) Y_4^2 as
     the manufactured solution (F = (20 - 5) Y_4^2), dt = 4e-3 (about 2.6
@@ -163,3 +163,27 @@ def test_imex_second_order_in_time(lib, sphere):
     e2 = rel(run(T / 50), fine)
     print(f"[imex] SBDF2 time errors {e1:.2e} {e2:.2e} ratio {e1 / e2:.2f}", flush=True)
     assert 3.3 < e1 / e2 < 4.8
+
+
+def test_imex_is_reproducible(lib, irregular):
+    """Two identical SBDF2 runs (graph-replayed iterations, fixed-order block
+    reductions) give the same bits, and the iteration counts agree."""
+    X, idx, W, op = irregular
+    u0, v0 = schnakenberg_ic(len(X))
+    kw = dict(order=2, D=(1.0, 10.0), reaction="schnakenberg", params=(0.1, 0.9, 50.0), maxit=500)
+    a, ia, ra = op.step_imex(dev(np.stack([u0, v0])), 1e-2, 10, **kw)
+    b, ib, rb_ = op.step_imex(dev(np.stack([u0, v0])), 1e-2, 10, **kw)
+    ha, hb = host(a), host(b)
+    assert ia == ib and ra == rb_
+    assert np.array_equal(ha.view(np.uint64), hb.view(np.uint64))
+
+
+def test_imex_zero_steps_and_zero_state(lib, sphere):
+    """nsteps = 0 returns the state unchanged; a zero state stays exactly zero
+    (the first residual is zero, so no iteration runs)."""
+    X, idx, W, op = sphere
+    u0 = real_sph_harm(3, 1, X)
+    got, its, _ = op.step_imex(dev(u0), 1e-2, 0, order=2)
+    assert its == 0 and np.array_equal(host(got)[0], u0)
+    z, its, res = op.step_imex(dev(np.zeros(len(X))), 1e-2, 3, order=2)
+    assert its == 0 and not np.any(host(z))
