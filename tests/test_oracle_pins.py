@@ -439,3 +439,40 @@ def test_kappa_mp_matches_fp64_where_fp64_resolves_it():
     k50 = stencil_kappa_mp(X[s], 0.05, kernel="imq", degree=0, dps=50)
     k80 = stencil_kappa_mp(X[s], 0.05, kernel="imq", degree=0, dps=80)
     assert k50 > 1e15 and abs(k50 / k80 - 1.0) < 1e-12
+
+
+def test_bisect_mp_against_two_node_closed_form():
+    """The high-precision bisection (Sec. 5) on two nodes at distance r with
+    the constant border (IMQ).  A~ = [[1, p, 1], [p, 1, 1], [1, 1, 0]] with
+    p = 1 / sqrt(1 + eps^2 r^2): (1, -1, 0) is an eigenvector with eigenvalue
+    1 - p, and on its complement A~ acts as [[1 + p, sqrt 2], [sqrt 2, 0]],
+    eigenvalues ((1 + p) +- sqrt((1 + p)^2 + 8)) / 2.  kappa_2(eps) from these
+    closed forms matches the oracle's eigenvalues, its root at kappa_T (found
+    to 40 digits) lies within tol / 2 of the returned eps, and a target the
+    bracket cannot reach gives status 2."""
+    import mpmath as mp
+
+    from oracle.truth import bisect_eps_mp, stencil_kappa_mp
+
+    r = 0.01
+    X = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+
+    def kappa_closed(e):
+        p = 1 / mp.sqrt(1 + (e * r) ** 2)
+        s = mp.sqrt((1 + p) ** 2 + 8)
+        lam = [abs(1 - p), abs(((1 + p) + s) / 2), abs(((1 + p) - s) / 2)]
+        return max(lam) / min(lam)
+
+    with mp.workdps(40):
+        for e in (0.5, 3.0, 20.0, 400.0):
+            k = stencil_kappa_mp(X, e, kernel="imq", degree=0)
+            assert abs(k / float(kappa_closed(mp.mpf(e))) - 1.0) < 1e-13, (e, k)
+        for kT in (1e3, 1e6, 1e8):
+            guess = math.sqrt(2 * 2.7320508 / kT) / r  # kappa ~ (1 + sqrt 3) / (eps^2 r^2 / 2) for small eps r
+            root = mp.findroot(lambda e: mp.log(kappa_closed(e)) - mp.log(kT), mp.mpf(guess))
+            eps, st = bisect_eps_mp(X, kT, kernel="imq", degree=0)
+            assert st == 0
+            assert abs(eps - float(root)) <= 0.5e-4 + 1e-12, (kT, eps, float(root))
+    # the bracket [0.05, 20] / rho halved at most 8 times cannot reach kappa_T = 1e12 here
+    _, st = bisect_eps_mp(X, 1e12, kernel="imq", degree=0)
+    assert st == 2
