@@ -237,3 +237,51 @@ def test_imex_bdf_order_on_explicit_reaction(order):
         assert v[0] == 0.0
     rates = [math.log2(errs[j] / errs[j + 1]) for j in range(2)]
     assert min(rates) > order - 0.2, (order, errs, rates)
+
+
+def _turing_linear_case(l, m):
+    """Small Y_l^m perturbation of (0, 0) on the unit sphere (icosahedral
+    nodes, N = 2562, n = 31, MQ with the degree-2 border at eps = 2) for the
+    Turing system with Table 1's spots kinetics and delta_v = 4.5e-3
+    (delta_u = 0.516 delta_v), and its exact linear evolution."""
+    import os
+
+    from scipy.linalg import expm
+
+    g = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split()
+            g[k] = float(v)
+    prm = {"alpha": g["turing_alpha"], "beta": g["turing_beta"], "gamma": g["turing_gamma"],
+           "tau1": g["turing_spots_tau1"], "tau2": g["turing_spots_tau2"]}
+    dv = 4.5e-3
+    D = [g["turing_delta_u_over_delta_v"] * dv, dv]
+    X, nrm = icosahedral_sphere(4)
+    idx = knn(X, 31)
+    W = build_weights(X, nrm, idx, 2.0)
+    Y = real_sph_harm(l, m, X)
+    k2 = l * (l + 1)
+    J = np.array([[prm["alpha"] - D[0] * k2, 1.0], [prm["gamma"], prm["beta"] - D[1] * k2]])
+    return X, idx, W, Y, prm, D, J, expm
+
+
+@pytest.mark.parametrize("l,m", [(5, 2), (9, 3)])
+def test_turing_linear_modes_follow_the_dispersion_relation(l, m):
+    """Linearised about (0, 0), eqs. turing1-turing2 read u_t = delta_u Lap u +
+    alpha u + v and v_t = delta_v Lap v + gamma u + beta v (the tau terms are
+    quadratic and cubic in the perturbation).  With Lap_S Y_l^m = -l(l+1) Y_l^m
+    the pair (u, v) = (a(t), b(t)) Y_l^m evolves as exp(J t) with
+    J = [[alpha - delta_u k^2, 1], [gamma, beta - delta_v k^2]], k^2 = l(l+1):
+    l = 5 decays (rate -0.108), l = 9 lies in the Turing band and grows
+    (+0.013).  The oracle's RK4 on its weights follows exp(J t) to the
+    operator's discretisation error over t = 20 from an amplitude of 1e-6."""
+    X, idx, W, Y, prm, D, J, expm = _turing_linear_case(l, m)
+    amp, T, dt = 1e-6, 20.0, 0.05
+    u, v = rk4(assemble(idx, W), [amp * Y, np.zeros_like(Y)], D, "turing", prm, dt=dt, nsteps=int(round(T / dt)))
+    E = expm(J * T)
+    ue, ve = E[0, 0] * amp * Y, E[1, 0] * amp * Y
+    eu = np.linalg.norm(u - ue) / np.linalg.norm(ue)
+    ev = np.linalg.norm(v - ve) / np.linalg.norm(ve)
+    assert eu < 2e-2 and ev < 2e-2, (l, eu, ev)

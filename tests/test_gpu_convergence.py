@@ -34,8 +34,8 @@ from oracle.knn import knn as oracle_knn
 from oracle.shape import bisect_eps, stencil_kappa
 from oracle.stepper import assemble, rk4
 from oracle.weights import build_weights as oracle_weights
-from synth import (bump_centres, icosahedral_sphere, sphere_forced, sphere_heat_series, staggered_torus,
-                   torus_angles, torus_forced)
+from synth import (bump_centres, icosahedral_sphere, real_sph_harm, sphere_forced, sphere_heat_series,
+                   staggered_torus, torus_angles, torus_forced)
 
 pytestmark = pytest.mark.gpu
 U64 = 2.0 ** -53
@@ -189,3 +189,44 @@ def test_convergence_orders(lib, name, schedule, stepper):
         # error falls with N over the first pairs (before FP64 saturation at the
         # capped targets), at no less than the floor order
         assert orders[0] >= FLOOR[n], (name, schedule, n, orders)
+
+
+@pytest.mark.parametrize("l,m", [(5, 2), (9, 3)])
+def test_turing_linear_modes_on_gpu(lib, l, m):
+    """The GPU's RK4 (FP64 and FP32 state, fused Turing kinetics) on a small
+    Y_l^m perturbation of (0, 0) against exp(J t) of the linearised system,
+    J = [[alpha - delta_u k^2, 1], [gamma, beta - delta_v k^2]], k^2 = l(l+1)
+    (Table 1 spots kinetics, delta_v = 4.5e-3; unit sphere, N = 2562, n = 31,
+    MQ + degree 2 at eps = 2, oracle weights), to the operator's
+    discretisation error over t = 20."""
+    import os
+
+    from scipy.linalg import expm
+
+    g = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "paper_facts.txt")):
+        line = line.split("#")[0].strip()
+        if line:
+            k, v = line.split()
+            g[k] = float(v)
+    params = (g["turing_alpha"], g["turing_beta"], g["turing_gamma"], g["turing_spots_tau1"], g["turing_spots_tau2"])
+    dv = 4.5e-3
+    D = (g["turing_delta_u_over_delta_v"] * dv, dv)
+    X, nrm = icosahedral_sphere(4)
+    idx = oracle_knn(X, 31)
+    W = oracle_weights(X, nrm, idx, 2.0)
+    _, perm = lib.knn(dev(X), 31)
+    op = lib.Operator(dev(idx, torch.int32), dev(W), perm=perm)
+    Y = real_sph_harm(l, m, X)
+    k2 = l * (l + 1)
+    J = np.array([[params[0] - D[0] * k2, 1.0], [params[2], params[1] - D[1] * k2]])
+    amp, T, dt = 1e-6, 20.0, 0.05
+    E = expm(J * T)
+    ue, ve = E[0, 0] * amp * Y, E[1, 0] * amp * Y
+    s0 = dev(np.stack([amp * Y, np.zeros_like(Y)]))
+    for prec in ("f64", "f32"):
+        u, v = host(op.step(s0, dt, int(round(T / dt)), prec=prec, D=D, reaction="turing", params=params))
+        eu = np.linalg.norm(u - ue) / np.linalg.norm(ue)
+        ev = np.linalg.norm(v - ve) / np.linalg.norm(ve)
+        print(f"[turing-linear] l={l} {prec}: |u - exact| {eu:.2e} |v - exact| {ev:.2e}", flush=True)
+        assert eu < 2e-2 and ev < 2e-2, (l, prec, eu, ev)
