@@ -254,6 +254,25 @@ __device__ __forceinline__ double sum_rows(double v, Shared<NB>& S, const Tid& t
         return red[6] + red[7];
     }
 }
+// Four sums over the rows held by lanes at once (see sum_rows).
+template <int NB>
+__device__ __forceinline__ void sum_rows4(double& a, double& b, double& c, double& d, Shared<NB>& S, const Tid& t) {
+    wave_sum4(a, b, c, d);
+    if constexpr (NB == 2) {
+        double* red = red_set(S.red, t);
+        if (t.cb == 0 && t.lane == 0) {
+            red[4 * t.rb] = a;
+            red[4 * t.rb + 1] = b;
+            red[4 * t.rb + 2] = c;
+            red[4 * t.rb + 3] = d;
+        }
+        bsync<NB>();
+        a = red[0] + red[4];
+        b = red[1] + red[5];
+        c = red[2] + red[6];
+        d = red[3] + red[7];
+    }
+}
 template <int NB>
 __device__ __forceinline__ double max_cols(double v, Shared<NB>& S, const Tid& t) {
     const double w = wave_max(v);
@@ -665,15 +684,15 @@ __device__ __forceinline__ void apply_q(const double (&a)[64], Shared<NB>& S, co
     }
 }
 
-// One wave (NB = 1), one vector: Q^T y (FWD) or Q y four reflectors at a time.
-// For a block H_{k0} .. H_{k0+3} the four products d_i = v_i . y are reduced
-// together, and the coupling of successive reflectors inside the block comes
-// from their Gram entries G_ij = v_i . v_j (S.G, six per block, from
-// reflector_gram): applying H_{k0} first, s_i = d_i - sum_{j<i} tau_j s_j G_ij
+// One wave (NB = 1), NV vectors: Q^T y (FWD) or Q y four reflectors at a time.
+// For a block H_{k0} .. H_{k0+3} the four products d_i = v_i . y of a vector
+// are reduced together, and the coupling of successive reflectors inside the
+// block comes from their Gram entries G_ij = v_i . v_j (S.G, six per block,
+// from reflector_gram): applying H_{k0} first, s_i = d_i - sum_{j<i} tau_j s_j G_ij
 // and y -= sum_i tau_i s_i v_i (the reverse order for Q y).  Rows past the last
 // reflector enter with v = 0 and tau = 0.
-template <int NB, bool FWD>
-__device__ __forceinline__ void apply_q_blocked(const double (&a)[64], Shared<NB>& S, double& y) {
+template <int NB, int NV, bool FWD>
+__device__ __forceinline__ void apply_q_blocked(const double (&a)[64], Shared<NB>& S, double (&y)[3]) {
     static_assert(NB == 1, "one-wave tiling only");
     const int p = S.m - 2;
 #pragma unroll
@@ -685,22 +704,34 @@ __device__ __forceinline__ void apply_q_blocked(const double (&a)[64], Shared<NB
             const double v2 = k0 + 2 < p ? a[k0 + 2] : 0.0, v3 = k0 + 3 < p ? a[k0 + 3] : 0.0;
             const double t0 = S.tau[k0], t1 = k0 + 1 < p ? S.tau[k0 + 1] : 0.0;
             const double t2 = k0 + 2 < p ? S.tau[k0 + 2] : 0.0, t3 = k0 + 3 < p ? S.tau[k0 + 3] : 0.0;
-            double d0 = v0 * y, d1 = v1 * y, d2 = v2 * y, d3 = v3 * y;
-            wave_sum4(d0, d1, d2, d3);
-            const double* G = S.G + 6 * b;  // G01 G02 G03 G12 G13 G23
-            double s0, s1, s2, s3;
-            if (FWD) {
-                s0 = d0;
-                s1 = fma(-t0 * s0, G[0], d1);
-                s2 = fma(-t1 * s1, G[3], fma(-t0 * s0, G[1], d2));
-                s3 = fma(-t2 * s2, G[5], fma(-t1 * s1, G[4], fma(-t0 * s0, G[2], d3)));
-            } else {
-                s3 = d3;
-                s2 = fma(-t3 * s3, G[5], d2);
-                s1 = fma(-t2 * s2, G[3], fma(-t3 * s3, G[4], d1));
-                s0 = fma(-t1 * s1, G[0], fma(-t2 * s2, G[1], fma(-t3 * s3, G[2], d0)));
+            double d[NV][4];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                d[q][0] = v0 * y[q];
+                d[q][1] = v1 * y[q];
+                d[q][2] = v2 * y[q];
+                d[q][3] = v3 * y[q];
             }
-            y = fma(-t3 * s3, v3, fma(-t2 * s2, v2, fma(-t1 * s1, v1, fma(-t0 * s0, v0, y))));
+#pragma unroll
+            for (int q = 0; q < NV; ++q) wave_sum4(d[q][0], d[q][1], d[q][2], d[q][3]);
+            const double* G = S.G + 6 * b;  // G01 G02 G03 G12 G13 G23
+            const double g01 = G[0], g02 = G[1], g03 = G[2], g12 = G[3], g13 = G[4], g23 = G[5];
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                double s0, s1, s2, s3;
+                if (FWD) {
+                    s0 = d[q][0];
+                    s1 = fma(-t0 * s0, g01, d[q][1]);
+                    s2 = fma(-t1 * s1, g12, fma(-t0 * s0, g02, d[q][2]));
+                    s3 = fma(-t2 * s2, g23, fma(-t1 * s1, g13, fma(-t0 * s0, g03, d[q][3])));
+                } else {
+                    s3 = d[q][3];
+                    s2 = fma(-t3 * s3, g23, d[q][2]);
+                    s1 = fma(-t2 * s2, g12, fma(-t3 * s3, g13, d[q][1]));
+                    s0 = fma(-t1 * s1, g01, fma(-t2 * s2, g02, fma(-t3 * s3, g03, d[q][0])));
+                }
+                y[q] = fma(-t3 * s3, v3, fma(-t2 * s2, v2, fma(-t1 * s1, v1, fma(-t0 * s0, v0, y[q]))));
+            }
         }
     }
 }
@@ -733,7 +764,7 @@ __device__ __forceinline__ void reflector_gram(const double (&a)[64], Shared<NB>
 template <int NB, int NV>
 __device__ __forceinline__ void solve(const double (&a)[64], Shared<NB>& S, const Tid& t, double (&y)[3]) {
     const int m = S.m;
-    if constexpr (NB == 1 && NV == 1) apply_q_blocked<NB, true>(a, S, y[0]);
+    if constexpr (NB == 1) apply_q_blocked<NB, NV, true>(a, S, y);
     else apply_q<NB, NV, true>(a, S, t, y);
     if (t.rb == 0) {
 #pragma unroll
@@ -745,7 +776,7 @@ __device__ __forceinline__ void solve(const double (&a)[64], Shared<NB>& S, cons
 #pragma unroll
     for (int v = 0; v < NV; ++v) y[v] = t.c < m ? S.rhs[v][t.c] : 0.0;
     bsync<NB>();
-    if constexpr (NB == 1 && NV == 1) apply_q_blocked<NB, false>(a, S, y[0]);
+    if constexpr (NB == 1) apply_q_blocked<NB, NV, false>(a, S, y);
     else apply_q<NB, NV, false>(a, S, t, y);
 }
 
@@ -804,7 +835,9 @@ __device__ __forceinline__ void solve_refined(const double (&a)[64], Shared<NB>&
 
 // --------------------------------------------------------------- border ----
 // Monomials in xi (order: 1, x, y, z, x^2, y^2, z^2, xy, xz, yz) at row
-// jr = 64 rb + lane, orthonormalised by MGS with one reorthogonalisation; kept
+// jr = 64 rb + lane, orthonormalised by classical Gram-Schmidt applied twice
+// (the projections on all earlier kept columns formed together, four sums at
+// a time, then subtracted; once more on the result); kept
 // columns go to S.U and their monomial coefficients to S.T.  A column is
 // dropped when its residual norm is at most rank_tol times the largest column
 // norm, that of the ones column (sqrt n; every |xi| <= 1), the analogue of a
@@ -844,13 +877,21 @@ __device__ __forceinline__ void build_border(Shared<NB>& S, const Tid& t, int de
         if (l < M) {
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
+                double cq[RMAX];
 #pragma unroll
-                for (int q = 0; q < RMAX; ++q) {  // constant trip count: u, tc, keep stay in registers
-                    if (q < l && keep[q]) {
-                        const double cq = sum_rows<NB>(u[q] * u[l], S, t);
-                        u[l] = fma(-cq, u[q], u[l]);
-                        tc[l] = fma(-cq, tc[q], tc[l]);
-                    }
+                for (int q0 = 0; q0 < l; q0 += 4) {  // constant trip counts: u, tc, keep stay in registers
+                    double g[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) g[i] = (q0 + i < l && keep[q0 + i]) ? u[q0 + i] * u[l] : 0.0;
+                    sum_rows4<NB>(g[0], g[1], g[2], g[3], S, t);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (q0 + i < l) cq[q0 + i] = g[i];
+                }
+#pragma unroll
+                for (int q = 0; q < l; ++q) {
+                    u[l] = fma(-cq[q], u[q], u[l]);
+                    tc[l] = fma(-cq[q], tc[q], tc[l]);
                 }
             }
             const double n2 = sum_rows<NB>(u[l] * u[l], S, t);
