@@ -433,36 +433,56 @@ __device__ __forceinline__ void amax_bounds(const Spectrum& sp, double& alo, dou
     ahi = fmax(-sp.lo1, sp.hi2);
 }
 
-// Up to `rounds` more 33-way multisection rounds on the brackets of lambda_1
-// (lanes 0..31) and lambda_m (lanes 32..63); with rel > 0 the rounds stop as
-// soon as both brackets are within 2 rel of the current estimate of
-// max |lambda| (midpoint error <= rel relative).
+// Up to `rounds` more multisection rounds on the brackets of lambda_1 and
+// lambda_m.  While both can still be max |lambda| = max(-lambda_1, lambda_m),
+// lanes 0..31 split lambda_1's bracket and lanes 32..63 lambda_m's 33 ways;
+// once one of them is ruled out (its magnitude bound lies below the other's),
+// all 64 lanes split the other's bracket 65 ways.  With rel > 0 the rounds
+// stop as soon as the bracket of max |lambda| is within 2 rel of its midpoint
+// (midpoint error <= rel relative).  sp.amax is that midpoint.
 template <int NB>
 __device__ __forceinline__ void spectrum_refine(const Shared<NB>& S, int lane, Spectrum& sp, int rounds,
                                                 double rel = 0.0) {
     const int m = S.m;
     double lo1 = sp.lo1, hi1 = sp.hi1, lo2 = sp.lo2, hi2 = sp.hi2;
-    const int g = lane >> 5, tt = lane & 31;
     for (int rd = 0; rd < rounds; ++rd) {
-        if (rel > 0.0) {  // uniform: the brackets are wave-uniform
-            const double est = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
-            if (fmax(hi1 - lo1, hi2 - lo2) <= 2.0 * rel * est) break;
+        // all conditions below are wave-uniform: the brackets are
+        const double alo = fmax(-hi1, lo2), ahi = fmax(-lo1, hi2);
+        if (rel > 0.0 && ahi - alo <= rel * (alo + ahi)) break;
+        const bool need1 = !(lo2 > -lo1);  // lambda_1 can still be the largest in magnitude
+        const bool need2 = !(-hi1 > hi2);  // lambda_m can
+        if (need1 && need2) {
+            const int g = lane >> 5, tt = lane & 31;
+            const double lo = g ? lo2 : lo1, hi = g ? hi2 : hi1;
+            const double sig = lo + (hi - lo) * (double)(tt + 1) / 33.0;
+            const int kidx = g ? m : 1;
+            const bool below = sturm<NB>(S, m, sig, sp.pivmin) < kidx;  // eigenvalue kidx lies above sig
+            const uint64_t bal = __ballot(below);
+            const int nb1 = __popcll(bal & 0xffffffffull);
+            const int nb2 = __popcll(bal >> 32);
+            const double n_lo1 = nb1 > 0 ? lo1 + (hi1 - lo1) * (double)nb1 / 33.0 : lo1;
+            const double n_hi1 = nb1 < 32 ? lo1 + (hi1 - lo1) * (double)(nb1 + 1) / 33.0 : hi1;
+            const double n_lo2 = nb2 > 0 ? lo2 + (hi2 - lo2) * (double)nb2 / 33.0 : lo2;
+            const double n_hi2 = nb2 < 32 ? lo2 + (hi2 - lo2) * (double)(nb2 + 1) / 33.0 : hi2;
+            lo1 = n_lo1; hi1 = n_hi1; lo2 = n_lo2; hi2 = n_hi2;
+        } else {
+            const double lo = need2 ? lo2 : lo1, hi = need2 ? hi2 : hi1;
+            const double sig = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+            const bool below = sturm<NB>(S, m, sig, sp.pivmin) < (need2 ? m : 1);
+            const int nb = __popcll(__ballot(below));
+            const double n_lo = nb > 0 ? lo + (hi - lo) * (double)nb / 65.0 : lo;
+            const double n_hi = nb < 64 ? lo + (hi - lo) * (double)(nb + 1) / 65.0 : hi;
+            if (need2) {
+                lo2 = n_lo;
+                hi2 = n_hi;
+            } else {
+                lo1 = n_lo;
+                hi1 = n_hi;
+            }
         }
-        const double lo = g ? lo2 : lo1, hi = g ? hi2 : hi1;
-        const double sig = lo + (hi - lo) * (double)(tt + 1) / 33.0;
-        const int kidx = g ? m : 1;
-        const bool below = sturm<NB>(S, m, sig, sp.pivmin) < kidx;  // eigenvalue kidx lies above sig
-        const uint64_t bal = __ballot(below);
-        const int nb1 = __popcll(bal & 0xffffffffull);
-        const int nb2 = __popcll(bal >> 32);
-        const double n_lo1 = nb1 > 0 ? lo1 + (hi1 - lo1) * (double)nb1 / 33.0 : lo1;
-        const double n_hi1 = nb1 < 32 ? lo1 + (hi1 - lo1) * (double)(nb1 + 1) / 33.0 : hi1;
-        const double n_lo2 = nb2 > 0 ? lo2 + (hi2 - lo2) * (double)nb2 / 33.0 : lo2;
-        const double n_hi2 = nb2 < 32 ? lo2 + (hi2 - lo2) * (double)(nb2 + 1) / 33.0 : hi2;
-        lo1 = n_lo1; hi1 = n_hi1; lo2 = n_lo2; hi2 = n_hi2;
     }
     sp.lo1 = lo1; sp.hi1 = hi1; sp.lo2 = lo2; sp.hi2 = hi2;
-    sp.amax = fmax(fabs(0.5 * (lo1 + hi1)), fabs(0.5 * (lo2 + hi2)));
+    sp.amax = 0.5 * (fmax(-hi1, lo2) + fmax(-lo1, hi2));
 }
 
 // Largest |lambda| of T to ~33^-rounds of the Gershgorin width (see
@@ -536,32 +556,59 @@ __device__ __forceinline__ void band_counts(const Shared<NB>& S, int lane, const
 }
 
 // Smallest |lambda| (geometric multisection on both sides of zero) within
-// [L, H]; nu = #eigenvalues below zero.  Rounds continue until the log
-// brackets are 2 rel wide (midpoint error <= rel relative), at most `rounds`.
+// [L, H]; nu = #eigenvalues below zero.  The candidates are lambda_{nu+1} > 0
+// and -lambda_nu > 0: while both can be the smaller, lanes 0..31 and 32..63
+// split their log brackets 33 ways; once one is ruled out (or does not
+// exist), all 64 lanes split the other's 65 ways.  Rounds continue until the
+// log bracket of min |lambda| is 2 rel wide (midpoint error <= rel relative),
+// at most `rounds`.
 template <int NB>
 __device__ __forceinline__ double spectrum_min_abs_in(const Shared<NB>& S, int lane, const Spectrum& sp, int nu,
                                                       double L, double H, int rounds, double rel) {
     const int m = S.m;
     double lp = log(L), hp = log(H), ln_ = log(L), hn = log(H);
-    const int g = lane >> 5, tt = lane & 31;
-    for (int rd = 0; rd < rounds && (hp - lp) > 2.0 * rel; ++rd) {
-        const double lo = g ? ln_ : lp, hi = g ? hn : hp;
-        const double sig = exp(lo + (hi - lo) * (double)(tt + 1) / 33.0);
-        bool above;  // target magnitude lies above sig
-        if (g == 0) above = sturm<NB>(S, m, sig, sp.pivmin) <= nu;   // lambda_{nu+1} > sig
-        else above = sturm<NB>(S, m, -sig, sp.pivmin) >= nu;         // lambda_nu < -sig
-        const uint64_t bal = __ballot(above);
-        const int nb1 = __popcll(bal & 0xffffffffull);
-        const int nb2 = __popcll(bal >> 32);
-        const double a1 = lp + (hp - lp) * (double)nb1 / 33.0, b1 = lp + (hp - lp) * (double)(nb1 + 1) / 33.0;
-        const double a2 = ln_ + (hn - ln_) * (double)nb2 / 33.0, b2 = ln_ + (hn - ln_) * (double)(nb2 + 1) / 33.0;
-        if (nb1 > 0) lp = a1;
-        if (nb1 < 32) hp = b1;
-        if (nb2 > 0) ln_ = a2;
-        if (nb2 < 32) hn = b2;
+    const bool has_pos = nu < m, has_neg = nu > 0;
+    for (int rd = 0; rd < rounds; ++rd) {
+        // wave-uniform: the brackets are
+        const bool need_p = has_pos && !(has_neg && lp > hn);
+        const bool need_n = has_neg && !(has_pos && ln_ > hp);
+        const double blo = need_p ? (need_n ? fmin(lp, ln_) : lp) : ln_;
+        const double bhi = need_p ? (need_n ? fmin(hp, hn) : hp) : hn;
+        if (!(bhi - blo > 2.0 * rel)) break;
+        if (need_p && need_n) {
+            const int g = lane >> 5, tt = lane & 31;
+            const double lo = g ? ln_ : lp, hi = g ? hn : hp;
+            const double sig = exp(lo + (hi - lo) * (double)(tt + 1) / 33.0);
+            bool above;  // target magnitude lies above sig
+            if (g == 0) above = sturm<NB>(S, m, sig, sp.pivmin) <= nu;   // lambda_{nu+1} > sig
+            else above = sturm<NB>(S, m, -sig, sp.pivmin) >= nu;         // lambda_nu < -sig
+            const uint64_t bal = __ballot(above);
+            const int nb1 = __popcll(bal & 0xffffffffull);
+            const int nb2 = __popcll(bal >> 32);
+            const double a1 = lp + (hp - lp) * (double)nb1 / 33.0, b1 = lp + (hp - lp) * (double)(nb1 + 1) / 33.0;
+            const double a2 = ln_ + (hn - ln_) * (double)nb2 / 33.0, b2 = ln_ + (hn - ln_) * (double)(nb2 + 1) / 33.0;
+            if (nb1 > 0) lp = a1;
+            if (nb1 < 32) hp = b1;
+            if (nb2 > 0) ln_ = a2;
+            if (nb2 < 32) hn = b2;
+        } else {
+            const double lo = need_p ? lp : ln_, hi = need_p ? hp : hn;
+            const double sig = exp(lo + (hi - lo) * (double)(lane + 1) / 65.0);
+            const bool above = need_p ? sturm<NB>(S, m, sig, sp.pivmin) <= nu : sturm<NB>(S, m, -sig, sp.pivmin) >= nu;
+            const int nb = __popcll(__ballot(above));
+            const double a1 = lo + (hi - lo) * (double)nb / 65.0, b1 = lo + (hi - lo) * (double)(nb + 1) / 65.0;
+            const double n_lo = nb > 0 ? a1 : lo, n_hi = nb < 64 ? b1 : hi;
+            if (need_p) {
+                lp = n_lo;
+                hp = n_hi;
+            } else {
+                ln_ = n_lo;
+                hn = n_hi;
+            }
+        }
     }
-    const double pos = nu < m ? exp(0.5 * (lp + hp)) : INFINITY;
-    const double neg = nu > 0 ? exp(0.5 * (ln_ + hn)) : INFINITY;
+    const double pos = has_pos ? exp(0.5 * (lp + hp)) : INFINITY;
+    const double neg = has_neg ? exp(0.5 * (ln_ + hn)) : INFINITY;
     return fmin(pos, neg);
 }
 
