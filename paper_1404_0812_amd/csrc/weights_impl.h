@@ -537,24 +537,6 @@ __device__ __forceinline__ void small_counts(const Shared<NB>& S, int lane, cons
     cb = c3 - c2;
 }
 
-// Band test and inertia in one pass: #eigenvalues with |lambda| < tau_a and
-// with |lambda| < tau_b (lanes 0-3), and nu = #eigenvalues below zero (lane 4).
-template <int NB>
-__device__ __forceinline__ void band_counts(const Shared<NB>& S, int lane, const Spectrum& sp, double tau_a,
-                                            double tau_b, int& ca, int& cb, int& nu) {
-    const int m = S.m;
-    double sig = 0.0;
-    if (lane == 0) sig = -tau_a;
-    if (lane == 1) sig = tau_a;
-    if (lane == 2) sig = -tau_b;
-    if (lane == 3) sig = tau_b;
-    const int c = lane < 5 ? sturm<NB>(S, m, sig, sp.pivmin) : 0;
-    const int c0 = __shfl(c, 0, 64), c1 = __shfl(c, 1, 64), c2 = __shfl(c, 2, 64), c3 = __shfl(c, 3, 64);
-    ca = c1 - c0;
-    cb = c3 - c2;
-    nu = __shfl(c, 4, 64);
-}
-
 // Smallest |lambda| (geometric multisection on both sides of zero) within
 // [L, H]; nu = #eigenvalues below zero.  The candidates are lambda_{nu+1} > 0
 // and -lambda_nu > 0: while both can be the smaller, lanes 0..31 and 32..63
@@ -563,10 +545,9 @@ __device__ __forceinline__ void band_counts(const Shared<NB>& S, int lane, const
 // log bracket of min |lambda| is 2 rel wide (midpoint error <= rel relative),
 // at most `rounds`.
 template <int NB>
-__device__ __forceinline__ double spectrum_min_abs_in(const Shared<NB>& S, int lane, const Spectrum& sp, int nu,
-                                                      double L, double H, int rounds, double rel) {
+__device__ __forceinline__ double min_abs_refine(const Shared<NB>& S, int lane, const Spectrum& sp, int nu, double lp,
+                                                 double hp, double ln_, double hn, int rounds, double rel) {
     const int m = S.m;
-    double lp = log(L), hp = log(H), ln_ = log(L), hn = log(H);
     const bool has_pos = nu < m, has_neg = nu > 0;
     for (int rd = 0; rd < rounds; ++rd) {
         // wave-uniform: the brackets are
@@ -610,6 +591,50 @@ __device__ __forceinline__ double spectrum_min_abs_in(const Shared<NB>& S, int l
     const double pos = has_pos ? exp(0.5 * (lp + hp)) : INFINITY;
     const double neg = has_neg ? exp(0.5 * (ln_ + hn)) : INFINITY;
     return fmin(pos, neg);
+}
+
+template <int NB>
+__device__ __forceinline__ double spectrum_min_abs_in(const Shared<NB>& S, int lane, const Spectrum& sp, int nu,
+                                                      double L, double H, int rounds, double rel) {
+    return min_abs_refine<NB>(S, lane, sp, nu, log(L), log(H), log(L), log(H), rounds, rel);
+}
+
+// The band test of a learned proposal and the first round of its min |lambda|
+// search in one Sturm pass: lanes 0-3 count the eigenvalues with
+// |lambda| < tau_a and < tau_b, lane 4 those below zero (nu), and lanes 8-35
+// / 36-63 split [tau_b, tau_a] (log scale) 29 ways on the positive / negative
+// side.  If the proposal is kept (ca > 0, cb == 0), min |lambda| lies in
+// [tau_b, tau_a), and the returned log brackets (lp, hp) and (ln_, hn) are
+// those after that first round.
+template <int NB>
+__device__ __forceinline__ void band_counts_min(const Shared<NB>& S, int lane, const Spectrum& sp, double tau_a,
+                                                double tau_b, int& ca, int& cb, int& nu, double& lp, double& hp,
+                                                double& ln_, double& hn) {
+    const int m = S.m;
+    const double l0 = log(tau_b), l1 = log(tau_a);
+    double sig = 0.0;
+    if (lane == 0) sig = -tau_a;
+    if (lane == 1) sig = tau_a;
+    if (lane == 2) sig = -tau_b;
+    if (lane == 3) sig = tau_b;
+    const bool pos_lane = lane >= 8 && lane < 36, neg_lane = lane >= 36;
+    if (pos_lane) sig = exp(l0 + (l1 - l0) * (double)(lane - 8 + 1) / 29.0);
+    if (neg_lane) sig = -exp(l0 + (l1 - l0) * (double)(lane - 36 + 1) / 29.0);
+    const int c = (lane < 5 || lane >= 8) ? sturm<NB>(S, m, sig, sp.pivmin) : 0;
+    const int c0 = __shfl(c, 0, 64), c1 = __shfl(c, 1, 64), c2 = __shfl(c, 2, 64), c3 = __shfl(c, 3, 64);
+    ca = c1 - c0;
+    cb = c3 - c2;
+    nu = __shfl(c, 4, 64);
+    // lambda_{nu+1} > sig (positive lanes), lambda_nu < sig (negative lanes)
+    const bool above = pos_lane ? c <= nu : (neg_lane ? c >= nu : false);
+    const uint64_t bal = __ballot(above);
+    const int nb1 = __popcll((bal >> 8) & 0xfffffffull);
+    const int nb2 = __popcll(bal >> 36);
+    lp = l0; hp = l1; ln_ = l0; hn = l1;
+    if (nb1 > 0) lp = l0 + (l1 - l0) * (double)nb1 / 29.0;
+    if (nb1 < 28) hp = l0 + (l1 - l0) * (double)(nb1 + 1) / 29.0;
+    if (nb2 > 0) ln_ = l0 + (l1 - l0) * (double)nb2 / 29.0;
+    if (nb2 < 28) hn = l0 + (l1 - l0) * (double)(nb2 + 1) / 29.0;
 }
 
 // Smallest |lambda| with no prior bracket: [1e-30, 1] x max |lambda|, 7 rounds.
@@ -1086,12 +1111,13 @@ __device__ __forceinline__ void process_stencil(const Job& J, int64_t s, Shared<
                 if (sp.finite && sp.amax > 0.0) {
                     int c_lo, c_hi, nu;  // |lambda| below amax/band_lo and below amax/band_hi
                     const double tau_lo = sp.amax / o.band_lo, tau_hi = sp.amax / o.band_hi;
-                    band_counts<NB>(S, t.lane, sp, tau_lo, tau_hi, c_lo, c_hi, nu);
+                    double lp, hp, ln_, hn;
+                    band_counts_min<NB>(S, t.lane, sp, tau_lo, tau_hi, c_lo, c_hi, nu, lp, hp, ln_, hn);
                     if (c_lo > 0 && c_hi == 0) {  // band_lo < kappa <= band_hi
                         need_bisect = false;
                         have_final = true;
-                        // min |lambda| lies in [tau_hi, tau_lo)
-                        amin_known = spectrum_min_abs_in<NB>(S, t.lane, sp, nu, tau_hi, tau_lo, 7, o.band_rel);
+                        // min |lambda| lies in [tau_hi, tau_lo): its first round is done
+                        amin_known = min_abs_refine<NB>(S, t.lane, sp, nu, lp, hp, ln_, hn, 6, o.band_rel);
                     }
                 }
             }
