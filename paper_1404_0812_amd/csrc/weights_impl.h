@@ -493,17 +493,23 @@ __device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, 
     Spectrum sp;
     // Gershgorin interval of T: each lane takes rows lane, lane + 64, then
     // wavefront min/max (exact, so the same bits as a serial scan)
-    double ngl = -INFINITY, gu = -INFINITY, emax2 = 0.0;
+    // and the extreme diagonal entries, Rayleigh quotients of unit vectors:
+    // lambda_1 <= min d_i and lambda_m >= max d_i
+    double ngl = -INFINITY, gu = -INFINITY, emax2 = 0.0, dmax = -INFINITY, ndmin = -INFINITY;
     bool fin = true;
     for (int i = lane; i < m; i += 64) {
         const double off = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i < m - 1 ? fabs(S.e[i]) : 0.0);
         ngl = fmax(ngl, off - S.d[i]);
         gu = fmax(gu, S.d[i] + off);
+        dmax = fmax(dmax, S.d[i]);
+        ndmin = fmax(ndmin, -S.d[i]);
         if (i < m - 1) emax2 = fmax(emax2, S.e2[i]);
         fin = fin && isfinite(S.d[i]) && (i == m - 1 || isfinite(S.e[i]));
     }
     double gl = -wave_max(ngl);
     gu = wave_max(gu);
+    dmax = wave_max(dmax);
+    const double dmin = -wave_max(ndmin);
     emax2 = wave_max(emax2);
     fin = __ballot(!fin) == 0;
     sp.finite = fin;
@@ -511,8 +517,11 @@ __device__ __forceinline__ Spectrum spectrum_max(const Shared<NB>& S, int lane, 
     const double w = gu - gl;
     gl -= 2.0 * w * 2.2e-16 + 2.0 * sp.pivmin;
     gu += 2.0 * w * 2.2e-16 + 2.0 * sp.pivmin;
-    sp.lo1 = sp.lo2 = gl;
-    sp.hi1 = sp.hi2 = gu;
+    sp.lo1 = gl;
+    sp.hi2 = gu;
+    // widened like the Gershgorin ends, for the counts' own rounding
+    sp.hi1 = fmin(gu, dmin + 2.0 * w * 2.2e-16 + 2.0 * sp.pivmin);
+    sp.lo2 = fmax(gl, dmax - 2.0 * w * 2.2e-16 - 2.0 * sp.pivmin);
     if (!fin) {
         sp.amax = NAN;
         return sp;
