@@ -324,63 +324,48 @@ __global__ __launch_bounds__(64) void k_knn(int64_t N, int n, Grid G, const doub
     int cnt = 0;
     double bound = INFINITY;  // current need-th best squared distance once known
     bool done = need == 0;
-    for (int R = 0; !done; ++R) {
-        // the shell of cells at Chebyshev distance R from the query's cell
-        for (int dx = -R; dx <= R; ++dx) {
-            int ix = cx + dx;
-            if (ix < 0 || ix >= G.g[0]) continue;
-            for (int dy = -R; dy <= R; ++dy) {
-                int iy = cy + dy;
-                if (iy < 0 || iy >= G.g[1]) continue;
-                bool edge_xy = (dx == -R || dx == R || dy == -R || dy == R);
-                for (int dz = -R; dz <= R; dz += (edge_xy ? 1 : 2 * R)) {
-                    int iz = cz + dz;
-                    if (iz >= 0 && iz < G.g[2]) {
-                        uint32_t k = morton3(ix, iy, iz);
-                        int s = start[k], e = start[k + 1];
-                        for (int b = s; b < e; b += 64) {
-                            int j = b + lane;
-                            double d2 = INFINITY;
-                            int oj = -1;
-                            bool ok = false;
-                            if (j < e) {
-                                double ddx = xs[j] - qx, ddy = ys[j] - qy, ddz = zs[j] - qz;
-                                d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
-                                oj = order[j];
-                                ok = (oj != q) && (d2 <= bound);
-                            }
-                            uint64_t m = __ballot(ok);
-                            int add = __popcll(m);
-                            if (add == 0) continue;
-                            if (cnt + add > KNN_CAP) {
-                                // keep only the best `need` candidates
-                                int S = next_pow2(cnt);
-                                for (int t = cnt + lane; t < S; t += 64) {
-                                    cd[t] = INFINITY;
-                                    cid[t] = 0x7fffffff;
-                                }
-                                __syncthreads();
-                                wave_bitonic(cd, cid, S);
-                                cnt = need;
-                                bound = cd[need - 1];
-                                ok = ok && (d2 <= bound);
-                                m = __ballot(ok);
-                                add = __popcll(m);
-                            }
-                            if (ok) {
-                                int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
-                                cd[pos] = d2;
-                                cid[pos] = oj;
-                            }
-                            cnt += add;
-                            __syncthreads();
-                        }
-                    }
-                    if (R == 0) break;
-                }
-            }
+    // One chunk of up to 64 candidates (point index j in cell order, valid
+    // when in range): squared distances, those within the bound appended to
+    // the LDS list; on overflow the list is cut to its best `need` first.
+    auto consider = [&](int j, bool valid) {
+        double d2 = INFINITY;
+        int oj = -1;
+        bool ok = false;
+        if (valid) {
+            double ddx = xs[j] - qx, ddy = ys[j] - qy, ddz = zs[j] - qz;
+            d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+            oj = order[j];
+            ok = (oj != q) && (d2 <= bound);
         }
-        // searched box: cells [c - R, c + R]; distance to its boundary
+        uint64_t m = __ballot(ok);
+        int add = __popcll(m);
+        if (add == 0) return;
+        if (cnt + add > KNN_CAP) {
+            // keep only the best `need` candidates
+            int S = next_pow2(cnt);
+            for (int t = cnt + lane; t < S; t += 64) {
+                cd[t] = INFINITY;
+                cid[t] = 0x7fffffff;
+            }
+            __syncthreads();
+            wave_bitonic(cd, cid, S);
+            cnt = need;
+            bound = cd[need - 1];
+            ok = ok && (d2 <= bound);
+            m = __ballot(ok);
+            add = __popcll(m);
+        }
+        if (ok) {
+            int pos = cnt + __popcll(m & ((1ull << lane) - 1ull));
+            cd[pos] = d2;
+            cid[pos] = oj;
+        }
+        cnt += add;
+        __syncthreads();
+    };
+    // After the shells up to R: sort, bound, and stop once the searched box
+    // provably holds the `need` nearest (or covers the whole grid).
+    auto settle = [&](int R) {
         bool covers = (cx - R <= 0) && (cy - R <= 0) && (cz - R <= 0) && (cx + R >= G.g[0] - 1) &&
                       (cy + R >= G.g[1] - 1) && (cz + R >= G.g[2] - 1);
         if (cnt >= need) {
@@ -406,6 +391,70 @@ __global__ __launch_bounds__(64) void k_knn(int64_t N, int n, Grid G, const doub
         } else if (covers) {
             done = true;  // cannot happen when n <= N
         }
+    };
+    if (!done) {
+        // R = 0 and 1 at once: the 27 cells of the 3 x 3 x 3 block, their point
+        // ranges read by 27 lanes together and swept as one list (in place of
+        // 27 sequential cell visits, each waiting on its range)
+        int s0 = 0, c0 = 0;
+        if (lane < 27) {
+            const int ix = cx + lane % 3 - 1, iy = cy + (lane / 3) % 3 - 1, iz = cz + lane / 9 - 1;
+            if (ix >= 0 && ix < G.g[0] && iy >= 0 && iy < G.g[1] && iz >= 0 && iz < G.g[2]) {
+                const uint32_t k = morton3(ix, iy, iz);
+                s0 = start[k];
+                c0 = start[k + 1] - s0;
+            }
+        }
+        // inclusive prefix sum of the counts over the wave
+        int incl = c0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int total = __shfl(incl, 63, 64);
+        __shared__ int cstart[27], cexcl[28];
+        if (lane < 27) {
+            cstart[lane] = s0;
+            cexcl[lane] = incl - c0;
+        }
+        if (lane == 0) cexcl[27] = total;
+        __syncthreads();
+        for (int b = 0; b < total; b += 64) {
+            const int t = b + lane;
+            int j = 0;
+            if (t < total) {
+                int lo = 0, hi = 26;  // the cell whose exclusive prefix is the last <= t
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (cexcl[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                j = cstart[lo] + (t - cexcl[lo]);
+            }
+            consider(j, t < total);
+        }
+        settle(1);
+    }
+    for (int R = 2; !done; ++R) {
+        // the shell of cells at Chebyshev distance R from the query's cell
+        for (int dx = -R; dx <= R; ++dx) {
+            int ix = cx + dx;
+            if (ix < 0 || ix >= G.g[0]) continue;
+            for (int dy = -R; dy <= R; ++dy) {
+                int iy = cy + dy;
+                if (iy < 0 || iy >= G.g[1]) continue;
+                bool edge_xy = (dx == -R || dx == R || dy == -R || dy == R);
+                for (int dz = -R; dz <= R; dz += (edge_xy ? 1 : 2 * R)) {
+                    int iz = cz + dz;
+                    if (iz >= 0 && iz < G.g[2]) {
+                        uint32_t k = morton3(ix, iy, iz);
+                        int s = start[k], e = start[k + 1];
+                        for (int b = s; b < e; b += 64) consider(b + lane, b + lane < e);
+                    }
+                }
+            }
+        }
+        settle(R);
     }
     int32_t* row = idx_out + (int64_t)q * n;
     if (lane == 0) row[0] = q;
