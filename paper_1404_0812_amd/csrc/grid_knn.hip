@@ -24,7 +24,15 @@ namespace {
 #ifndef KNN_CELL_SCALE
 #define KNN_CELL_SCALE 1.0  // cell edge relative to the expected stencil radius
 #endif
-constexpr int KNN_CAP = 1024;  // candidate buffer per query (entries)
+// Candidate buffer per query (entries; a power of two for the bitonic sort).
+// At least need + 64 = 191 for n <= 128, so that a chunk fits after a cut.
+// 512 holds the ~430 candidates of the 27 cells at n = 50 without a cut and
+// keeps the LDS per query at 6 KB: the search is latency-bound, and 1024
+// entries (12 KB) let half as many queries run per CU (7.5 vs 4.9 ms at
+// N = 1e6, n = 50; 17.5 vs 10.9 ms at n = 101); 256 cuts every n = 101 query
+// at least once (14.4 ms).
+constexpr int KNN_CAP = 512;
+static_assert(KNN_CAP >= 127 + 64 && (KNN_CAP & (KNN_CAP - 1)) == 0, "candidate buffer");
 constexpr int MAX_BITS = 9;    // Morton bits per axis (2^27 cells at most)
 
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {
