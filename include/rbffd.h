@@ -390,7 +390,7 @@ typedef struct {
  * (s_2, t_2, s_3, t_3, ..., zero padding) with (s_j, t_j) the offsets
  * x_j - x_1 in the tangent frame (tau_1 along the nearest neighbour's
  * projected offset, tau_2 = nu x tau_1) divided by rho.  rho (nullable): N
- * FP64 stencil radii.  Requires 2 <= n <= 65. */
+ * FP64 stencil radii.  Requires 2 <= n <= 64 (RBFFD_E_ARG otherwise). */
 int rbffd_mlp_features(rbffd_ctx ctx, int64_t N, const double* xyz, const double* nrm, const int32_t* idx,
                        int32_t n, uint16_t* feats, double* rho);
 /* y[B] (FP32) = network(feats[B x 128]). */
@@ -405,7 +405,8 @@ int rbffd_mlp_grad(rbffd_ctx ctx, const float* params, int64_t B, const uint16_t
 int rbffd_mlp_train(rbffd_ctx ctx, float* params, float* adam_m, float* adam_v, int64_t count,
                     const uint16_t* feats, const float* target, const rbffd_train_opts* opts,
                     float* loss_per_step);
-/* eps[N] (FP64) = exp(network(features)) / rho for the stencils idx. */
+/* eps[N] (FP64) = exp(network(features)) / rho for the stencils idx (the
+ * features of rbffd_mlp_features: 2 <= n <= 64). */
 int rbffd_predict_eps(rbffd_ctx ctx, const float* params, int64_t N, const double* xyz, const double* nrm,
                       const int32_t* idx, int32_t n, double* eps);
 

@@ -79,22 +79,27 @@ struct Bf16Params {
     const float* P;       // FP32 parameters (biases, w3, b3)
 };
 
-// Forward (and optionally backward) over one tile of TB samples.
-// mode 0: forward only, writes y.  mode 1: forward + backward, accumulates
-// gradients into grad (FP32, atomics) and the summed squared error into loss.
-// Sample s of the tile is row base + s of x, or a hashed index when sampling.
+// Forward (and, when TRAIN, backward) over one tile of TB samples.
+// TRAIN false: forward only, writes y.  TRAIN true: forward + backward,
+// accumulates gradients into grad (FP32, atomics) and the summed squared
+// error into loss.  Sample s of the tile is row base + s of x, or a hashed
+// index when sampling.  The forward-only form keeps only the two row-major
+// tiles in LDS (32 KB instead of 128 KB: five workgroups per CU instead of
+// one); its arithmetic is the same, so y is the same bit for bit.
+template <bool TRAIN>
 __global__ __launch_bounds__(WG) void k_mlp(int64_t count, Bf16Params prm, const uint16_t* __restrict__ x,
-                                            const float* __restrict__ target, float* __restrict__ y, int mode,
+                                            const float* __restrict__ target, float* __restrict__ y,
                                             float* __restrict__ grad, float* __restrict__ loss, float gscale,
                                             uint64_t seed, int64_t step) {
     __shared__ __attribute__((aligned(16))) uint16_t Xs[TB * F];   // [b][k]
-    __shared__ __attribute__((aligned(16))) uint16_t XT[F * TB];   // [k][b]
     __shared__ __attribute__((aligned(16))) uint16_t H1s[TB * H];  // [b][i]
-    __shared__ __attribute__((aligned(16))) uint16_t H1T[H * TB];  // [i][b]
-    __shared__ __attribute__((aligned(16))) uint16_t H2s[TB * H];  // [b][o]
-    __shared__ __attribute__((aligned(16))) uint16_t G2s[TB * H];  // dH2 [b][o]
-    __shared__ __attribute__((aligned(16))) uint16_t G2T[H * TB];  // dH2 [o][b]
-    __shared__ __attribute__((aligned(16))) uint16_t G1T[H * TB];  // dH1 [i][b]
+    // backward only
+    __shared__ __attribute__((aligned(16))) uint16_t XT[TRAIN ? F * TB : 8];   // [k][b]
+    __shared__ __attribute__((aligned(16))) uint16_t H1T[TRAIN ? H * TB : 8];  // [i][b]
+    __shared__ __attribute__((aligned(16))) uint16_t H2s[TRAIN ? TB * H : 8];  // [b][o]
+    __shared__ __attribute__((aligned(16))) uint16_t G2s[TRAIN ? TB * H : 8];  // dH2 [b][o]
+    __shared__ __attribute__((aligned(16))) uint16_t G2T[TRAIN ? H * TB : 8];  // dH2 [o][b]
+    __shared__ __attribute__((aligned(16))) uint16_t G1T[TRAIN ? H * TB : 8];  // dH1 [i][b]
     __shared__ float ys[TB], dys[TB];
     __shared__ int64_t rows[TB];
     const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
@@ -113,9 +118,11 @@ __global__ __launch_bounds__(WG) void k_mlp(int64_t count, Bf16Params prm, const
         uint4 v = make_uint4(0, 0, 0, 0);
         if (rr < count) v = *reinterpret_cast<const uint4*>(x + rr * F + k8);
         *reinterpret_cast<uint4*>(Xs + b * F + k8) = v;
-        const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
+        if constexpr (TRAIN) {
+            const uint16_t* hv = reinterpret_cast<const uint16_t*>(&v);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) XT[(k8 + t) * TB + b] = hv[t];
+            for (int t = 0; t < 8; ++t) XT[(k8 + t) * TB + b] = hv[t];
+        }
     }
     __syncthreads();
     const int r0 = wv * 16;              // this wave's 16 sample rows
@@ -131,7 +138,7 @@ __global__ __launch_bounds__(WG) void k_mlp(int64_t count, Bf16Params prm, const
             const int b = r0 + rq + i;
             const uint16_t h = f2bf(fmaxf(acc[i] + bb, 0.0f));
             H1s[b * H + o] = h;
-            H1T[o * TB + b] = h;
+            if constexpr (TRAIN) H1T[o * TB + b] = h;
         }
     }
     __syncthreads();
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(WG) void k_mlp(int64_t count, Bf16Params prm, const
         for (int i = 0; i < 4; ++i) {
             const int b = r0 + rq + i;
             const uint16_t h = f2bf(fmaxf(acc[i] + bb, 0.0f));
-            H2s[b * H + o] = h;
+            if constexpr (TRAIN) H2s[b * H + o] = h;
             part[i] = fmaf(bf2f(h), w3, part[i]);
         }
     }
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(WG) void k_mlp(int64_t count, Bf16Params prm, const
         for (int i = 0; i < 4; ++i) ys[r0 + rq + i] = part[i] + prm.P[OFF_B3];
     }
     __syncthreads();
-    if (mode == 0) {
+    if constexpr (!TRAIN) {
         if (tid < TB && base + tid < count) y[base + tid] = ys[tid];
         return;
     }
@@ -276,63 +283,76 @@ __global__ void k_adam(float* __restrict__ P, float* __restrict__ M, float* __re
     }
 }
 
-// Features: one wavefront per stencil, lane j = stencil slot j.
+// Features: one wavefront per FEAT_SPW consecutive stencils, lane j = stencil
+// slot j (n <= 64; 2 (n - 1) <= 126 entries of the F = 128, the rest zero).  The loads of all of them are issued before any is used (stencils
+// beyond N read stencil N - 1 and write nothing), so each wavefront has
+// FEAT_SPW round trips to memory in flight instead of one.
+constexpr int FEAT_SPW = 4;
 __global__ __launch_bounds__(64) void k_features(int64_t N, int n, const double* __restrict__ xyz,
                                                  const double* __restrict__ nrm, const int32_t* __restrict__ idx,
                                                  uint16_t* __restrict__ feat, double* __restrict__ rho_out) {
-    __shared__ double t1s[3];
+    __shared__ double t1s[FEAT_SPW][3];
     const int l = threadIdx.x;
-    const int64_t s = blockIdx.x;
-    if (s >= N) return;
+    const int64_t s0 = (int64_t)blockIdx.x * FEAT_SPW;
+    double dx[FEAT_SPW], dy[FEAT_SPW], dz[FEAT_SPW], nx[FEAT_SPW], ny[FEAT_SPW], nz[FEAT_SPW], rho[FEAT_SPW];
     // indices outside [0, N) read node 0 and make rho NaN (the proposal is then
     // unusable and the weights call flags the stencil)
-    int c = idx[s * n];
-    bool bad = c < 0 || c >= N;
-    if (bad) c = 0;
-    const double cx = xyz[3 * (int64_t)c], cy = xyz[3 * (int64_t)c + 1], cz = xyz[3 * (int64_t)c + 2];
-    double dx = 0, dy = 0, dz = 0;
-    if (l < n) {
-        int j = idx[s * n + l];
+#pragma unroll
+    for (int u = 0; u < FEAT_SPW; ++u) {
+        const int64_t s = s0 + u < N ? s0 + u : N - 1;
+        int c = idx[s * n];
+        bool bad = c < 0 || c >= N;
+        if (bad) c = 0;
+        int j = l < n ? idx[s * n + l] : c;
         if (j < 0 || j >= N) {
             bad = true;
             j = 0;
         }
-        dx = xyz[3 * (int64_t)j] - cx;
-        dy = xyz[3 * (int64_t)j + 1] - cy;
-        dz = xyz[3 * (int64_t)j + 2] - cz;
-    }
-    double r2 = (dx * dx + dy * dy) + dz * dz;
+        const double cx = xyz[3 * (int64_t)c], cy = xyz[3 * (int64_t)c + 1], cz = xyz[3 * (int64_t)c + 2];
+        const double px = xyz[3 * (int64_t)j], py = xyz[3 * (int64_t)j + 1], pz = xyz[3 * (int64_t)j + 2];
+        dx[u] = l < n ? px - cx : 0.0;
+        dy[u] = l < n ? py - cy : 0.0;
+        dz[u] = l < n ? pz - cz : 0.0;
+        nx[u] = nrm[3 * (int64_t)c];
+        ny[u] = nrm[3 * (int64_t)c + 1];
+        nz[u] = nrm[3 * (int64_t)c + 2];
+        double r2 = (dx[u] * dx[u] + dy[u] * dy[u]) + dz[u] * dz[u];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
-    const bool any_bad = __ballot(bad) != 0;
-    const double rho = any_bad ? NAN : sqrt(r2);
-    double nx = nrm[3 * (int64_t)c], ny = nrm[3 * (int64_t)c + 1], nz = nrm[3 * (int64_t)c + 2];
-    const double nn = sqrt(nx * nx + ny * ny + nz * nz);
-    nx /= nn; ny /= nn; nz /= nn;
-    if (l == 1) {
-        // tau_1: the nearest neighbour's offset projected on the tangent plane
-        const double dn = dx * nx + dy * ny + dz * nz;
-        double tx = dx - dn * nx, ty = dy - dn * ny, tz = dz - dn * nz;
-        double tn = sqrt(tx * tx + ty * ty + tz * tz);
-        if (!(tn > 1e-12 * rho)) {  // degenerate: any tangent direction
-            const bool ax = fabs(nx) < 0.9;
-            tx = ax ? 0.0 : -nz; ty = ax ? nz : 0.0; tz = ax ? -ny : nx;
-            tn = sqrt(tx * tx + ty * ty + tz * tz);
+        for (int o = 32; o > 0; o >>= 1) r2 = fmax(r2, __shfl_xor(r2, o, 64));
+        const bool any_bad = __ballot(bad) != 0;
+        rho[u] = any_bad ? NAN : sqrt(r2);
+        const double nn = sqrt(nx[u] * nx[u] + ny[u] * ny[u] + nz[u] * nz[u]);
+        nx[u] /= nn; ny[u] /= nn; nz[u] /= nn;
+        if (l == 1) {
+            // tau_1: the nearest neighbour's offset projected on the tangent plane
+            const double dn = dx[u] * nx[u] + dy[u] * ny[u] + dz[u] * nz[u];
+            double tx = dx[u] - dn * nx[u], ty = dy[u] - dn * ny[u], tz = dz[u] - dn * nz[u];
+            double tn = sqrt(tx * tx + ty * ty + tz * tz);
+            if (!(tn > 1e-12 * rho[u])) {  // degenerate: any tangent direction
+                const bool ax = fabs(nx[u]) < 0.9;
+                tx = ax ? 0.0 : -nz[u]; ty = ax ? nz[u] : 0.0; tz = ax ? -ny[u] : nx[u];
+                tn = sqrt(tx * tx + ty * ty + tz * tz);
+            }
+            t1s[u][0] = tx / tn; t1s[u][1] = ty / tn; t1s[u][2] = tz / tn;
         }
-        t1s[0] = tx / tn; t1s[1] = ty / tn; t1s[2] = tz / tn;
     }
     __syncthreads();
-    const double ax = t1s[0], ay = t1s[1], az = t1s[2];
-    const double bx = ny * az - nz * ay, by = nz * ax - nx * az, bz = nx * ay - ny * ax;
-    uint16_t* f = feat + s * F;
-    if (l >= 1 && l < n) {
-        const float sv = (float)((dx * ax + dy * ay + dz * az) / rho);
-        const float tv = (float)((dx * bx + dy * by + dz * bz) / rho);
-        f[2 * (l - 1)] = f2bf(sv);
-        f[2 * (l - 1) + 1] = f2bf(tv);
+#pragma unroll
+    for (int u = 0; u < FEAT_SPW; ++u) {
+        const int64_t s = s0 + u;
+        if (s >= N) break;
+        const double ax = t1s[u][0], ay = t1s[u][1], az = t1s[u][2];
+        const double bx = ny[u] * az - nz[u] * ay, by = nz[u] * ax - nx[u] * az, bz = nx[u] * ay - ny[u] * ax;
+        uint16_t* f = feat + s * F;
+        if (l >= 1 && l < n) {
+            const float sv = (float)((dx[u] * ax + dy[u] * ay + dz[u] * az) / rho[u]);
+            const float tv = (float)((dx[u] * bx + dy[u] * by + dz[u] * bz) / rho[u]);
+            f[2 * (l - 1)] = f2bf(sv);
+            f[2 * (l - 1) + 1] = f2bf(tv);
+        }
+        for (int k = 2 * (n - 1) + l; k < F; k += 64) f[k] = 0;
+        if (l == 0 && rho_out) rho_out[s] = rho[u];
     }
-    for (int k = 2 * (n - 1) + l; k < F; k += 64) f[k] = 0;
-    if (l == 0 && rho_out) rho_out[s] = rho;
 }
 
 __global__ void k_eps_from_y(int64_t N, const float* __restrict__ y, const double* __restrict__ rho,
@@ -368,9 +388,10 @@ extern "C" int rbffd_mlp_features(rbffd_ctx ctx, int64_t N, const double* xyz, c
     if (!ctx) return RBFFD_E_ARG;
     if (N < 0) return set_error(ctx, RBFFD_E_ARG, "N < 0");
     if (N == 0) return RBFFD_OK;
-    if (n < 2 || 2 * (n - 1) > F) return set_error(ctx, RBFFD_E_ARG, "features need 2 <= n <= %d", F / 2 + 1);
+    if (n < 2 || n > 64) return set_error(ctx, RBFFD_E_ARG, "features need 2 <= n <= 64 (one lane per slot)");
     if (!xyz || !nrm || !idx || !feats) return set_error(ctx, RBFFD_E_ARG, "null pointer");
-    hipLaunchKernelGGL(k_features, dim3((unsigned)N), dim3(64), 0, ctx->stream, N, n, xyz, nrm, idx, feats, rho);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((N + FEAT_SPW - 1) / FEAT_SPW)), dim3(64), 0, ctx->stream, N, n,
+                       xyz, nrm, idx, feats, rho);
     HIP_TRY(ctx, hipGetLastError());
     return RBFFD_OK;
 }
@@ -385,8 +406,8 @@ extern "C" int rbffd_mlp_forward(rbffd_ctx ctx, const float* params, int64_t B, 
     if (rc) return rc;
     convert(ctx->stream, params, ms);
     Bf16Params p{ms.W1, ms.W2, ms.W2T, params};
-    hipLaunchKernelGGL(k_mlp, dim3((unsigned)((B + TB - 1) / TB)), dim3(WG), 0, ctx->stream, B, p, feats, nullptr, y,
-                       0, nullptr, nullptr, 0.0f, (uint64_t)0, (int64_t)0);
+    hipLaunchKernelGGL(k_mlp<false>, dim3((unsigned)((B + TB - 1) / TB)), dim3(WG), 0, ctx->stream, B, p, feats,
+                       nullptr, y, nullptr, nullptr, 0.0f, (uint64_t)0, (int64_t)0);
     HIP_TRY(ctx, hipGetLastError());
     return RBFFD_OK;
 }
@@ -403,8 +424,8 @@ extern "C" int rbffd_mlp_grad(rbffd_ctx ctx, const float* params, int64_t B, con
     HIP_TRY(ctx, hipMemsetAsync(grad, 0, RBFFD_MLP_PARAMS * sizeof(float), ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(loss, 0, sizeof(float), ctx->stream));
     Bf16Params p{ms.W1, ms.W2, ms.W2T, params};
-    hipLaunchKernelGGL(k_mlp, dim3((unsigned)((B + TB - 1) / TB)), dim3(WG), 0, ctx->stream, B, p, feats, target,
-                       nullptr, 1, grad, loss, 1.0f / (float)B, (uint64_t)0, (int64_t)0);
+    hipLaunchKernelGGL(k_mlp<true>, dim3((unsigned)((B + TB - 1) / TB)), dim3(WG), 0, ctx->stream, B, p, feats,
+                       target, nullptr, grad, loss, 1.0f / (float)B, (uint64_t)0, (int64_t)0);
     HIP_TRY(ctx, hipGetLastError());
     return RBFFD_OK;
 }
@@ -432,7 +453,7 @@ extern "C" int rbffd_mlp_train(rbffd_ctx ctx, float* params, float* adam_m, floa
     for (int64_t s = 0; s < o->steps; ++s) {
         float* lp = loss_per_step ? loss_per_step + s : loss_tmp;
         HIP_TRY(ctx, hipMemsetAsync(lp, 0, sizeof(float), st));
-        hipLaunchKernelGGL(k_mlp, dim3(nb), dim3(WG), 0, st, count, p, feats, target, nullptr, 1, grad, lp,
+        hipLaunchKernelGGL(k_mlp<true>, dim3(nb), dim3(WG), 0, st, count, p, feats, target, nullptr, grad, lp,
                            1.0f / (float)o->batch, o->seed, o->step0 + s);
         const double t = (double)(o->step0 + s + 1);
         const float c1 = (float)(1.0 / (1.0 - pow(o->beta1, t)));
@@ -451,7 +472,7 @@ extern "C" int rbffd_predict_eps(rbffd_ctx ctx, const float* params, int64_t N, 
     if (N < 0) return set_error(ctx, RBFFD_E_ARG, "N < 0");
     if (N == 0) return RBFFD_OK;
     if (!params || !xyz || !nrm || !idx || !eps) return set_error(ctx, RBFFD_E_ARG, "null pointer");
-    if (n < 2 || 2 * (n - 1) > F) return set_error(ctx, RBFFD_E_ARG, "features need 2 <= n <= %d", F / 2 + 1);
+    if (n < 2 || n > 64) return set_error(ctx, RBFFD_E_ARG, "features need 2 <= n <= 64 (one lane per slot)");
     MlpScratch ms;
     char* extra = nullptr;
     const size_t fbytes = (size_t)N * F * sizeof(uint16_t);
@@ -462,10 +483,11 @@ extern "C" int rbffd_predict_eps(rbffd_ctx ctx, const float* params, int64_t N, 
     double* rho = (double*)(extra + ((fbytes + 255) & ~(size_t)255));
     float* y = (float*)((char*)rho + ((rbytes + 255) & ~(size_t)255));
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(k_features, dim3((unsigned)N), dim3(64), 0, st, N, n, xyz, nrm, idx, feats, rho);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((N + FEAT_SPW - 1) / FEAT_SPW)), dim3(64), 0, st, N, n, xyz, nrm,
+                       idx, feats, rho);
     convert(st, params, ms);
     Bf16Params p{ms.W1, ms.W2, ms.W2T, params};
-    hipLaunchKernelGGL(k_mlp, dim3((unsigned)((N + TB - 1) / TB)), dim3(WG), 0, st, N, p, feats, nullptr, y, 0,
+    hipLaunchKernelGGL(k_mlp<false>, dim3((unsigned)((N + TB - 1) / TB)), dim3(WG), 0, st, N, p, feats, nullptr, y,
                        nullptr, nullptr, 0.0f, (uint64_t)0, (int64_t)0);
     hipLaunchKernelGGL(k_eps_from_y, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, N, y, rho, eps);
     HIP_TRY(ctx, hipGetLastError());

@@ -30,9 +30,13 @@ def bf16_bits(a):
     return (np.asarray(omlp.bf16(a), dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16)
 
 
-def test_features_match_oracle(lib):
+# N = 2999 and 1001 leave the last wavefront of four stencils partly empty;
+# n = 64 uses every lane of the wavefront (its largest stencil)
+@pytest.mark.parametrize("N,n", [(3000, 50), (2999, 50), (1001, 64)])
+def test_features_match_oracle(lib, N, n):
     X, nrm = blob(3000, oversample=2.0)
-    idx = oracle_knn(X, 50)
+    X, nrm = X[:N], nrm[:N]
+    idx = oracle_knn(X, n)
     f, rho = lib.mlp_features(dev(X), dev(nrm), dev(idx, torch.int32))
     got = bf16_to_f64(f)
     ref, rref = omlp.features(X, nrm, idx)
@@ -44,6 +48,13 @@ def test_features_match_oracle(lib):
     big = np.abs(refq) > 1e-12
     assert np.mean(got[big] != refq[big]) < 1e-3
     assert np.allclose(rho.cpu().numpy(), rref, rtol=1e-15)
+
+
+def test_features_reject_stencils_wider_than_a_wavefront(lib):
+    X, nrm = blob(3000, oversample=2.0)
+    idx = oracle_knn(X[:500], 65)
+    with pytest.raises(lib.RbffdError, match="n <= 64"):
+        lib.mlp_features(dev(X[:500]), dev(nrm[:500]), dev(idx, torch.int32))
 
 
 @pytest.fixture(scope="module")
