@@ -270,24 +270,39 @@ __device__ int prefilter(double* cd, int* cid, int cnt, int need) {
             if (t < cnt) lm[g] = fmin(lm[g], cd[t]);
         }
     }
-    // rank of each group minimum among all 64 NG (ties by (group, lane))
-    int rank[NG];
-#pragma unroll
-    for (int g = 0; g < NG; ++g) rank[g] = 0;
-    for (int o = 0; o < 64; ++o) {
-#pragma unroll
-        for (int h = 0; h < NG; ++h) {
-            const double v = __shfl(lm[h], o, 64);
-#pragma unroll
-            for (int g = 0; g < NG; ++g)
-                rank[g] += (v < lm[g] || (v == lm[g] && (h < g || (h == g && o < lane)))) ? 1 : 0;
-        }
-    }
     double bound = INFINITY;
+    if constexpr (NG == 1) {
+        // the need-th smallest of the 64 minima: bitonic sort across the lanes
+        double v = lm[0];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        const uint64_t who = __ballot(rank[g] == need - 1);
-        if (who) bound = __shfl(lm[g], __ffsll((unsigned long long)who) - 1, 64);
+        for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const double o = __shfl_xor(v, j, 64);
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                v = keep_min ? fmin(v, o) : fmax(v, o);
+            }
+        }
+        bound = __shfl(v, need - 1, 64);
+    } else {
+        // rank of each group minimum among all 64 NG (ties by (group, lane))
+        int rank[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) rank[g] = 0;
+        for (int o = 0; o < 64; ++o) {
+#pragma unroll
+            for (int h = 0; h < NG; ++h) {
+                const double v = __shfl(lm[h], o, 64);
+#pragma unroll
+                for (int g = 0; g < NG; ++g)
+                    rank[g] += (v < lm[g] || (v == lm[g] && (h < g || (h == g && o < lane)))) ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const uint64_t who = __ballot(rank[g] == need - 1);
+            if (who) bound = __shfl(lm[g], __ffsll((unsigned long long)who) - 1, 64);
+        }
     }
     int kept = 0;
     for (int b = 0; b < cnt; b += 64) {
