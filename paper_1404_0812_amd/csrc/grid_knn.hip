@@ -394,6 +394,10 @@ __global__ __launch_bounds__(64) void k_knn(int64_t N, int n, Grid G, const doub
         if (cnt >= need) {
             if (need <= 64 && cnt > 128) cnt = prefilter<1>(cd, cid, cnt, need);
             else if (need <= 128 && cnt > 256) cnt = prefilter<2>(cd, cid, cnt, need);
+            // a second pass over the survivors (groups of one or two) usually
+            // leaves at most 64 (128) to sort
+            if (need <= 64 && cnt > 64) cnt = prefilter<1>(cd, cid, cnt, need);
+            else if (need <= 128 && cnt > 128) cnt = prefilter<2>(cd, cid, cnt, need);
             int S = next_pow2(cnt);
             for (int t = cnt + lane; t < S; t += 64) {
                 cd[t] = INFINITY;
