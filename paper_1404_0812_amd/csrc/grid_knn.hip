@@ -220,8 +220,36 @@ __device__ __forceinline__ bool key_less(double da, int ia, double db, int ib) {
 }
 
 // Bitonic sort of the first S (power of two) entries of the wave's buffer.
+// Up to 64 entries: one per lane, exchanged across the lanes in registers (no
+// barrier between the stages); entries S..63 of the network are padding
+// (+inf, INT_MAX) that sorts last, and only the first S are written back.
 __device__ void wave_bitonic(double* d2, int* id, int S) {
     const int lane = threadIdx.x;
+    if (S <= 64) {
+        double v = lane < S ? d2[lane] : INFINITY;
+        int x = lane < S ? id[lane] : 0x7fffffff;
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const double ov = __shfl_xor(v, j, 64);
+                const int ox = __shfl_xor(x, j, 64);
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                const bool take = keep_min ? key_less(ov, ox, v, x) : key_less(v, x, ov, ox);
+                if (take) {
+                    v = ov;
+                    x = ox;
+                }
+            }
+        }
+        __syncthreads();  // every lane has read its entry
+        if (lane < S) {
+            d2[lane] = v;
+            id[lane] = x;
+        }
+        __syncthreads();
+        return;
+    }
     for (int k = 2; k <= S; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int t = lane; t < S; t += 64) {
