@@ -94,7 +94,7 @@ typedef struct {
     double band_lo;       /* LEARNED acceptance band for kappa_2; also the band for */
     double band_hi;       /*   band_stop */
     double rank_tol;      /* relative drop tolerance for border columns */
-    int32_t band_stop;    /* BISECT: 1 = stop as soon as kappa_2 is inside the band */
+    int32_t band_stop;    /* BISECT and the LEARNED fallback: 1 = stop as soon as kappa_2 is inside the band */
     int32_t max_expand;   /* bracket expansions allowed on each side */
 } rbffd_weight_opts;
 

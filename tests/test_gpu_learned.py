@@ -53,6 +53,36 @@ def test_learned_mode_band_check_and_fallback(lib, torus):
             assert abs(eg[i] - eo) <= 2e-4
 
 
+def test_band_stopped_fallback(lib, torus):
+    """With band_stop the fallback bisection ends as soon as kappa_2 is inside
+    the band: kept proposals are untouched (bit for bit), fallback stencils end
+    inside [1e11, 1e13] (oracle kappa_2 at the GPU's eps) after fewer kappa_2
+    evaluations than the bisection to the paper's tolerance."""
+    X, nrm, idx = torus
+    rho = np.sqrt(np.max(np.sum((X[idx] - X[idx[:, :1]]) ** 2, axis=2), axis=1))
+    rng = np.random.default_rng(4)
+    prop = rng.uniform(0.45, 0.7, size=len(X)) / rho
+    args = (dev(X), dev(nrm), 50)
+    kw = dict(idx=dev(idx, torch.int32), eps_in=dev(prop), eps_mode="learned", kappa_target=1e12, band=(1e11, 1e13))
+    full = lib.build_weights(*args, **kw)
+    stop = lib.build_weights(*args, band_stop=True, **kw)
+    torch.cuda.synchronize()
+    st = stop.status.cpu().numpy()
+    assert np.array_equal(st, full.status.cpu().numpy())
+    kept, fb = st == 0, st == 1
+    assert kept.any() and fb.any()
+    for name in ("w", "eps", "kappa", "nevals"):
+        a, b = getattr(full, name).cpu().numpy(), getattr(stop, name).cpu().numpy()
+        assert np.array_equal(a[kept], b[kept]), name
+    ks, ns, nf = stop.kappa.cpu().numpy(), stop.nevals.cpu().numpy(), full.nevals.cpu().numpy()
+    assert np.all((ks[fb] > 1e11) & (ks[fb] <= 1e13))
+    assert np.mean(ns[fb]) < np.mean(nf[fb])
+    es = stop.eps.cpu().numpy()
+    for i in rng.choice(np.flatnonzero(fb), min(20, int(fb.sum())), replace=False):
+        k = stencil_kappa(X[idx[i]], es[i])
+        assert 1e11 * (1 - 1e-3) < k <= 1e13 * (1 + 1e-3)
+
+
 def test_kept_proposals_report_kappa_low_band(lib, torus):
     """Well-conditioned band [1e5, 1e7]: proposals at the bisected eps for
     kappa_T = 1e6 are all kept, and their kappa_2 (eigenvalue search stopped at
