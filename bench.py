@@ -6,10 +6,8 @@ One step = one pass of the whole hot path over the point-cloud workload
   sparse operator -> `--rk4-steps` FP32 RK4 steps (default 10000).
 `value` is stencil weights per second (N / time of stencils + eps + weights);
 `ms_per_rk4_step` is the time of one RK4 step.  The shape parameter comes from
-the learned model when a trained model is available (`--eps learned`; a
-proposal whose kappa_2 falls outside the band is replaced by bisection toward
-kappa_T that stops as soon as kappa_2 is inside the band, the acceptance rule of
-the proposals themselves), else from bisection (`--eps bisect`).
+the learned model with bisection fallback when a trained model is available
+(`--eps learned`), else from bisection (`--eps bisect`).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--rk4-steps R]
 """
@@ -423,7 +421,7 @@ def run_bench(args, torch, X, nrm, pool):
             eps_hat = net.predict_eps(Xd, Nd, idx)
             e1b = ev()
             res = rb.build_weights(Xd, Nd, n, idx=idx, eps_in=eps_hat, ctx=ctx, eps_mode="learned",
-                                   kappa_target=args.kappa, band=band, band_stop=True)
+                                   kappa_target=args.kappa, band=band)
         else:
             e1b = e1
             res = rb.build_weights(Xd, Nd, n, idx=idx, ctx=ctx, eps_mode="bisect", kappa_target=args.kappa)
@@ -536,10 +534,10 @@ def run_bench(args, torch, X, nrm, pool):
             eps_hat = net_.predict_eps(Xd, Nd, idx_c)
             b = ev()
             torch.cuda.synchronize()
-            _, out_c["learned"] = timed_weights(eps_mode="learned", eps_in=eps_hat, band_stop=True)
+            _, out_c["learned"] = timed_weights(eps_mode="learned", eps_in=eps_hat)
             out_c["learned"]["predict_ms"] = a.elapsed_time(b)
             eps_c = learned.constant_eps(Xd, Nd, idx_c, c_const_, ctx=ctx)
-            _, out_c["constant_eps_rho"] = timed_weights(eps_mode="learned", eps_in=eps_c, band_stop=True)
+            _, out_c["constant_eps_rho"] = timed_weights(eps_mode="learned", eps_in=eps_c)
             out_c["constant_eps_rho"]["c"] = c_const_
             L = out_c["learned"]["ms"] + out_c["learned"]["predict_ms"]
             # primary figure: the same acceptance band for both (equal achieved
@@ -678,8 +676,7 @@ def run_bench(args, torch, X, nrm, pool):
         "dtype": "f64 weights / f32 state / bf16 mlp",
         "data": "synthetic",
         "config": {"workload": f"implicit blob point cloud N={args.N}, n={n}, MQ + degree-2 border, "
-                               f"eps {args.eps} (kappa band [{band[0]:g},{band[1]:g}], bisection toward kappa_T={args.kappa:g}"
-                               f"{' stopped inside the band for the proposals it replaces' if args.eps == 'learned' else ''}), "
+                               f"eps {args.eps} (kappa band [{band[0]:g},{band[1]:g}], bisection to kappa_T={args.kappa:g}), "
                                f"Schnakenberg FP32 RK4 x{args.rk4_steps}", "N": args.N, "n": n,
                    "rk4_steps": args.rk4_steps, "rk4_dt": dt_rk4, "rho_L": rho_hat, "eps_mode": args.eps},
         "phases_ms": med,
