@@ -8,6 +8,7 @@ import torch
 
 from oracle.knn import knn as oracle_knn
 from oracle.shape import bisect_eps, stencil_kappa
+from oracle.weights import build_weights as oracle_weights
 from synth import ellipsoid, jittered_torus, torus_grid_for_count
 
 pytestmark = pytest.mark.gpu
@@ -78,9 +79,16 @@ def test_band_stopped_fallback(lib, torus):
     assert np.all((ks[fb] > 1e11) & (ks[fb] <= 1e13))
     assert np.mean(ns[fb]) < np.mean(nf[fb])
     es = stop.eps.cpu().numpy()
-    for i in rng.choice(np.flatnonzero(fb), min(20, int(fb.sum())), replace=False):
-        k = stencil_kappa(X[idx[i]], es[i])
-        assert 1e11 * (1 - 1e-3) < k <= 1e13 * (1 + 1e-3)
+    rows = rng.choice(np.flatnonzero(fb), min(20, int(fb.sum())), replace=False)
+    kap = np.array([stencil_kappa(X[idx[i]], es[i]) for i in rows])
+    assert np.all((kap > 1e11 * (1 - 1e-3)) & (kap <= 1e13 * (1 + 1e-3)))
+    # the weights are those of the stopping eps (oracle at the GPU's eps,
+    # per row within 0.5 kappa u as in the other weight parity tests)
+    wo = oracle_weights(X, nrm, idx, es, rows=rows)
+    wg = stop.w.cpu().numpy()[rows]
+    err = np.linalg.norm(wg - wo, axis=1) / np.linalg.norm(wo, axis=1)
+    print(f"[band-stop] max err/(kappa u) = {np.max(err / (kap * 2.0 ** -53)):.4f}", flush=True)
+    assert np.all(err <= np.maximum(1e-9, 0.5 * kap * 2.0 ** -53))
 
 
 def test_kept_proposals_report_kappa_low_band(lib, torus):
