@@ -220,11 +220,54 @@ __device__ __forceinline__ bool key_less(double da, int ia, double db, int ib) {
 }
 
 // Bitonic sort of the first S (power of two) entries of the wave's buffer.
-// Up to 64 entries: one per lane, exchanged across the lanes in registers (no
-// barrier between the stages); entries S..63 of the network are padding
-// (+inf, INT_MAX) that sorts last, and only the first S are written back.
+// Up to 128 entries: entries lane and lane + 64 in registers, exchanged across
+// the lanes (no barrier between the stages); up to 64 only the first half.
+// Entries S.. of the network are padding (+inf, INT_MAX) that sorts last, and
+// only the first S are written back.
+__device__ __forceinline__ void lane_exchange(double& v, int& x, int pos, int j, int k) {
+    const double ov = __shfl_xor(v, j, 64);
+    const int ox = __shfl_xor(x, j, 64);
+    const bool keep_min = ((pos & j) == 0) == ((pos & k) == 0);
+    const bool take = keep_min ? key_less(ov, ox, v, x) : key_less(v, x, ov, ox);
+    if (take) {
+        v = ov;
+        x = ox;
+    }
+}
 __device__ void wave_bitonic(double* d2, int* id, int S) {
     const int lane = threadIdx.x;
+    if (S > 64 && S <= 128) {
+        double v0 = d2[lane], v1 = lane + 64 < S ? d2[lane + 64] : INFINITY;
+        int x0 = id[lane], x1 = lane + 64 < S ? id[lane + 64] : 0x7fffffff;
+#pragma unroll
+        for (int k = 2; k <= 128; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                if (j == 64) {  // the pair (lane, lane + 64) is in one lane
+                    const bool asc = (lane & k) == 0;
+                    const bool sw = asc ? key_less(v1, x1, v0, x0) : key_less(v0, x0, v1, x1);
+                    if (sw) {
+                        const double tv = v0;
+                        const int tx = x0;
+                        v0 = v1; x0 = x1;
+                        v1 = tv; x1 = tx;
+                    }
+                } else {
+                    lane_exchange(v0, x0, lane, j, k);
+                    lane_exchange(v1, x1, lane + 64, j, k);
+                }
+            }
+        }
+        __syncthreads();  // every lane has read its entries
+        d2[lane] = v0;
+        id[lane] = x0;
+        if (lane + 64 < S) {
+            d2[lane + 64] = v1;
+            id[lane + 64] = x1;
+        }
+        __syncthreads();
+        return;
+    }
     if (S <= 64) {
         double v = lane < S ? d2[lane] : INFINITY;
         int x = lane < S ? id[lane] : 0x7fffffff;
