@@ -356,24 +356,28 @@ __device__ int prefilter(double* cd, int* cid, int cnt, int need) {
         }
         bound = __shfl(v, need - 1, 64);
     } else {
-        // rank of each group minimum among all 64 NG (ties by (group, lane))
-        int rank[NG];
+        static_assert(NG == 2, "64 or 128 groups");
+        // 128 minima, lm[0] and lm[1] of every lane: the same sort, two per lane
+        double v0 = lm[0], v1 = lm[1];
 #pragma unroll
-        for (int g = 0; g < NG; ++g) rank[g] = 0;
-        for (int o = 0; o < 64; ++o) {
+        for (int k = 2; k <= 128; k <<= 1) {
 #pragma unroll
-            for (int h = 0; h < NG; ++h) {
-                const double v = __shfl(lm[h], o, 64);
-#pragma unroll
-                for (int g = 0; g < NG; ++g)
-                    rank[g] += (v < lm[g] || (v == lm[g] && (h < g || (h == g && o < lane)))) ? 1 : 0;
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                if (j == 64) {  // the pair (lane, lane + 64) is in one lane
+                    const bool asc = (lane & k) == 0;
+                    const double lo = fmin(v0, v1), hi = fmax(v0, v1);
+                    v0 = asc ? lo : hi;
+                    v1 = asc ? hi : lo;
+                } else {
+                    const double o0 = __shfl_xor(v0, j, 64), o1 = __shfl_xor(v1, j, 64);
+                    const bool m0 = ((lane & j) == 0) == ((lane & k) == 0);
+                    const bool m1 = (((lane + 64) & j) == 0) == (((lane + 64) & k) == 0);
+                    v0 = m0 ? fmin(v0, o0) : fmax(v0, o0);
+                    v1 = m1 ? fmin(v1, o1) : fmax(v1, o1);
+                }
             }
         }
-#pragma unroll
-        for (int g = 0; g < NG; ++g) {
-            const uint64_t who = __ballot(rank[g] == need - 1);
-            if (who) bound = __shfl(lm[g], __ffsll((unsigned long long)who) - 1, 64);
-        }
+        bound = need - 1 < 64 ? __shfl(v0, need - 1, 64) : __shfl(v1, need - 1 - 64, 64);
     }
     int kept = 0;
     for (int b = 0; b < cnt; b += 64) {
